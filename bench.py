@@ -1,0 +1,143 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit S_N transport step on one MI355X.
+
+Workload: the lattice benchmark on a 700 x 700 grid with 256 ordinates
+(8 Gauss-Legendre polar x 32 azimuths), minmod second order, Heun, CFL 0.5
+(640 steps to T = 3.2). One step = both Heun stages with their scalar-flux
+epilogues and QoI reductions over the whole grid. Inputs are synthetic (the
+problem statement itself) and resident in HBM before timing starts.
+
+Prints one JSON line. `value` = cell-ordinate updates per second (one update
+= one (cell, ordinate) advanced one full time step). `roofline` describes the
+dominant kernel (Heun stage 2) against 8 TB/s; `cpu_baseline` times the FP64
+oracle on a bounded sample of the same workload on the host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(problem, plan_info, kind):
+    """Algorithmic HBM bytes of one stage launch over the whole grid.
+
+    Per cell-ordinate: Heun stage 1 / Euler read psi and write psi (2 s);
+    Heun stage 2 reads psi^(1) and psi^n and writes psi^(n+1) (3 s). Per cell:
+    the incoming scalar flux (4 B), the outgoing one (4 B), the region id (1 B).
+    Halo re-reads, partial-flux groups and padding are not algorithmic.
+    """
+    s = 2 if problem.psi_dtype == "bf16" else 4
+    cells = problem.nx * problem.ny
+    per_co = {0: 2 * s, 1: 2 * s, 2: 3 * s}[kind]
+    return cells * problem.M * per_co + cells * 9
+
+
+def cpu_baseline(problem, budget_s=15.0):
+    """Time the oracle (as it stands) on whole Heun steps of the workload."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.threads(0)
+    psi = np.zeros((problem.M, problem.ny, problem.nx))
+    t0 = time.perf_counter()
+    psi, _ = oracle.advance(problem, psi, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(50, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    psi, _ = oracle.advance(problem, psi, steps)
+    secs = time.perf_counter() - t0
+    ups = problem.cell_ordinates * steps / secs
+    return {"value": ups, "unit": "cell-ordinate updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} Heun steps of the {problem.nx}x{problem.ny}x{problem.M} lattice "
+                      f"(FP64, {threads} OpenMP threads, {secs:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=640)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU angular split is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2505_17284_amd import inputs as I
+    from paper_2505_17284_amd import solver
+
+    problem = I.config(2).replace(psi_dtype=args.dtype)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    plan = solver.Plan(problem, group_size=args.group, rows_per_wave=args.rows, device="cuda:0")
+    info = plan.info
+    print(f"[bench] plan: {info}", file=sys.stderr, flush=True)
+    plan.run(args.warmup, unbounded=True)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(args.steps, unbounded=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ms, counts = plan.kernel_ms()
+    plan.set_timing(False)
+    print(f"[bench] timed {args.steps} steps in {secs:.4f} s; kernel ms {ms} counts {counts}",
+          file=sys.stderr, flush=True)
+
+    ups = problem.cell_ordinates * args.steps / secs
+    kind = 2  # Heun stage 2 dominates (3 psi accesses per cell-ordinate)
+    avg_ms = ms[kind] / max(counts[kind], 1)
+    bytes_launch = algorithmic_bytes(problem, info, kind)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    stage1_ms = ms[1] / max(counts[1], 1)
+    stage1_gbs = algorithmic_bytes(problem, info, 1) / (stage1_ms * 1e-3) / 1e9
+    step_bytes = algorithmic_bytes(problem, info, 1) + algorithmic_bytes(problem, info, 2)
+    line = {
+        "metric": "cell-ordinate updates/s",
+        "value": ups,
+        "unit": "cell-ordinate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "lattice700_M256_heun2", "nx": problem.nx, "ny": problem.ny,
+                   "ordinates": problem.M, "order": problem.order, "stepper": "heun",
+                   "cfl": problem.cfl, "psi_storage": args.dtype,
+                   "group_size": info["group_size"], "rows_per_wave": info["rows_per_wave"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sn_stage_kernel<2, kAverage> (Heun stage 2)",
+                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_launch},
+        "stage1": {"kernel_avg_ms": stage1_ms, "achieved_GBs": stage1_gbs},
+        "step_algorithmic_GBs": step_bytes / (secs / args.steps) / 1e9,
+        "roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / (step_bytes / problem.cell_ordinates),
+    }
+    plan.close()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

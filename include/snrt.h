@@ -1,0 +1,211 @@
+/*
+ * snrt.h -- C ABI of the MI355X explicit S_N transport step.
+ *
+ * The library advances the discrete-ordinates system of arXiv 2505.17284
+ * (Sec. 4.1, eq. eq_sn_2d: M ordinates on the upper hemisphere, weights summing
+ * to 2 pi, isotropic scattering through phi = sum_l w_l psi_l, isotropic source)
+ * with the upwind finite-volume balance of Sec. 4.2 (eqs. eq_sn_2d_eqn_fv,
+ * eq_upwind1stOrder) on a uniform Cartesian grid of square cells, first-order
+ * or minmod-limited second-order reconstruction, ghost-cell boundaries (end of
+ * Sec. 4.2), and forward Euler or Heun's method (Sec. 4.3, eq. eq_ODE) with
+ * dt = T / N_t, N_t = ceil(T / (CFL h) - 1e-9) (Sec. 5.1.3). Along the way it
+ * accumulates the quantities of interest of Sec. 3.1.2 / 3.2.2: particle mass,
+ * absorption per tally region, outflow and inflow through rectangle boundaries,
+ * instantaneous and integrated over time.
+ *
+ * Conventions
+ *  - Every call returns sn_status; SN_OK is 0. Nothing throws across the ABI.
+ *    The text of the last failure on the calling thread is sn_last_error().
+ *  - Host input arrays belong to the caller and are read (and copied) only
+ *    during the call that receives them.
+ *  - Device buffers belong to the caller (the Python layer allocates them with
+ *    PyTorch) and are lent to a plan by sn_plan_bind; the library never frees
+ *    them. The plan owns only host memory and HIP events.
+ *  - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *    legacy default stream). Calls that launch work are asynchronous unless
+ *    documented as synchronising; asynchronous device faults are reported as
+ *    SN_ERR_DEVICE by the next synchronising call.
+ *  - A plan is not thread-safe: one thread at a time may call into it.
+ */
+#ifndef SNRT_H
+#define SNRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SN_MAX_TALLIES 8   /* absorption tally regions */
+#define SN_MAX_RECTS 4     /* outflow/inflow rectangles */
+#define SN_MAX_REGIONS 256 /* material regions (uint8 ids) */
+#define SN_MAX_ORDINATES 4096
+
+typedef int32_t sn_status;
+#define SN_OK 0
+#define SN_ERR_INVALID 1     /* argument or problem statement rejected */
+#define SN_ERR_OOM 2         /* host allocation failed, or buffers too small */
+#define SN_ERR_DEVICE 3      /* a HIP call failed */
+#define SN_ERR_UNSUPPORTED 4 /* valid request the library does not implement */
+#define SN_ERR_NONFINITE 5   /* a QoI became NaN or infinite */
+#define SN_ERR_BUSY 6        /* admission refused: over the memory budget */
+#define SN_ERR_STATE 7       /* call out of order (e.g. run before bind/init) */
+
+/* Boundary kinds per side, sides ordered W (x = x0), E, S (y = y0), N. */
+#define SN_BC_VACUUM 0  /* ghost value 0 */
+#define SN_BC_INFLOW 1  /* isotropic inflow value inflow[side] */
+#define SN_BC_REFLECT 2 /* ghost = mirror ordinate's value in the boundary cell */
+
+#define SN_EULER 0
+#define SN_HEUN 1
+
+#define SN_F32 0  /* psi stored as IEEE binary32 */
+#define SN_BF16 1 /* psi stored as bfloat16 (round to nearest even), math in FP32 */
+
+/* A problem statement (Sec. 4.1 with the benchmark data of Sec. 3).
+ *
+ *  nx, ny, h      grid of nx * ny square cells of side h > 0; cell (i, j),
+ *                 i along x, covers [i h, (i+1) h] x [j h, (j+1) h] relative to
+ *                 the lower-left corner.
+ *  M, xi, eta, w  ordinates: direction cosines along x and y and weights, [M]
+ *                 each; sum w must equal 2 pi to 1e-10 relative (Sec. 4.1).
+ *  mirror_x/_y    [M] index of the ordinate with xi (eta) negated and equal
+ *                 weight; required when a side is SN_BC_REFLECT (checked
+ *                 bit-exactly), otherwise may be NULL.
+ *  region         [ny][nx] row-major material id of every cell, < n_regions.
+ *  sigma_a/s, q   [n_regions] absorption and scattering cross-sections
+ *                 (>= 0, finite) and isotropic source per ordinate (finite).
+ *  tally          [n_regions] absorption tally id (< n_tallies <= 8).
+ *  bc, inflow     boundary kind and inflow value per side (W, E, S, N).
+ *  order          1 (first-order upwind) or 2 (minmod MUSCL, boundary faces
+ *                 first order).
+ *  stepper        SN_EULER or SN_HEUN.
+ *  cfl, t_end     dt = t_end / N_t with N_t = ceil(t_end / (cfl h) - 1e-9).
+ *  rects          [n_rects][4] = (i0, j0, i1, j1), half-open cell ranges
+ *                 0 <= i0 < i1 <= nx, 0 <= j0 < j1 <= ny; the outflow and
+ *                 inflow through each rectangle's boundary are QoIs.
+ *  psi_dtype      SN_F32 or SN_BF16.
+ */
+typedef struct sn_problem {
+    int32_t nx, ny;
+    double h;
+    int32_t M;
+    const double *xi, *eta, *w;
+    const int32_t *mirror_x, *mirror_y;
+    const uint8_t *region;
+    int32_t n_regions;
+    const double *sigma_a, *sigma_s, *q;
+    const uint8_t *tally;
+    int32_t n_tallies;
+    int32_t bc[4];
+    double inflow[4];
+    int32_t order;
+    int32_t stepper;
+    double cfl, t_end;
+    int32_t n_rects;
+    const int32_t *rects;
+    int32_t psi_dtype;
+} sn_problem;
+
+/* Sizes and derived constants of a plan. psi_bytes is the size of ONE angular
+ * flux buffer; a plan needs two (A and B) plus one scratch buffer, each
+ * 256-byte aligned. The device layout of psi is [M][ny][pitch] elements,
+ * x fastest, pitch >= nx. */
+typedef struct sn_plan_info {
+    int32_t n_steps;   /* N_t */
+    double dt;
+    int32_t nx, ny, M, pitch;
+    int32_t n_groups;  /* ordinate groups (phi partials per cell) */
+    int32_t group_size;
+    int32_t rows_per_wave;
+    int32_t n_workgroups; /* workgroups of one stage launch */
+    uint64_t psi_bytes;
+    uint64_t scratch_bytes;
+    int32_t psi_dtype;
+    int32_t step;      /* steps taken so far */
+} sn_plan_info;
+
+/* QoIs of the current state (instantaneous) and their time integrals over
+ * [0, t], integrated with the rule of the stepper: Euler dt q(psi^n); Heun
+ * dt/2 (q(psi^n) + q(psi^(1))). balance_residual = mass(t) - [mass(0) +
+ * int (source + inflow_domain - outflow_domain - sum absorption) dt], where
+ * rectangle 0 is taken as the domain boundary when it covers the whole grid
+ * (0 otherwise). */
+typedef struct sn_qoi {
+    int64_t step;
+    double t;
+    int32_t n_tallies, n_rects;
+    double mass, source;
+    double absorption[SN_MAX_TALLIES];
+    double outflow[SN_MAX_RECTS];
+    double inflow[SN_MAX_RECTS];
+    double int_mass, int_source;
+    double int_absorption[SN_MAX_TALLIES];
+    double int_outflow[SN_MAX_RECTS];
+    double int_inflow[SN_MAX_RECTS];
+    double balance_residual;
+    int32_t nonfinite; /* 1 if any QoI became NaN or infinite */
+} sn_qoi;
+
+typedef struct sn_plan sn_plan;
+
+/* Validate a problem statement and build a plan (host only; no device work).
+ * Copies every input array. Returns SN_ERR_INVALID with the reason in
+ * sn_last_error() for a statement the method does not define. */
+sn_status sn_plan_create(const sn_problem *problem, sn_plan **out);
+
+/* Same, with explicit launch shape: group_size ordinates per workgroup and
+ * rows_per_wave rows per wavefront (0 = library default). */
+sn_status sn_plan_create_tuned(const sn_problem *problem, int32_t group_size,
+                               int32_t rows_per_wave, sn_plan **out);
+
+sn_status sn_plan_get_info(const sn_plan *plan, sn_plan_info *out);
+
+/* Lend device buffers: psi_a and psi_b of info.psi_bytes each, scratch of
+ * info.scratch_bytes; all 256-byte aligned, non-overlapping, valid until the
+ * plan is destroyed or rebound. */
+sn_status sn_plan_bind(sn_plan *plan, void *psi_a, void *psi_b, void *scratch);
+
+/* Upload the plan's tables, set psi to psi0 (host [M][ny][nx] float32, or
+ * NULL for psi0 = 0 as in both benchmarks), reset step and QoI integrals.
+ * Asynchronous on `stream`; psi0 is copied before the call returns. */
+sn_status sn_plan_init(sn_plan *plan, const float *psi0, void *stream);
+
+/* Advance min(n_steps, N_t - step) time steps. Asynchronous. */
+sn_status sn_plan_run(sn_plan *plan, int32_t n_steps, void *stream);
+
+/* Advance exactly n_steps (may go past N_t; used for timing). Asynchronous. */
+sn_status sn_plan_run_unbounded(sn_plan *plan, int32_t n_steps, void *stream);
+
+/* QoIs of the current state and the integrals so far. Synchronises `stream`.
+ * Returns SN_ERR_NONFINITE (with *out filled) if any QoI is not finite. */
+sn_status sn_plan_qoi(sn_plan *plan, sn_qoi *out, void *stream);
+
+/* Copy the current psi to host [M][ny][nx] float32 (BF16 widened exactly).
+ * Synchronises `stream`. */
+sn_status sn_plan_read_psi(const sn_plan *plan, float *host_out, void *stream);
+
+/* Copy the current scalar flux phi = sum_k w_k psi_k to host [ny][nx]
+ * float32 (the FP32 value the next stage uses). Synchronises `stream`. */
+sn_status sn_plan_read_phi(const sn_plan *plan, float *host_out, void *stream);
+
+/* Capture `steps_per_graph` steps (even, >= 2; 0 disables) into a hipGraph
+ * and replay it in sn_plan_run. */
+sn_status sn_plan_use_graph(sn_plan *plan, int32_t steps_per_graph);
+
+/* Per-kernel timing: when on, sn_plan_run records HIP events around every
+ * stage launch on the launch stream. sn_plan_kernel_ms returns the summed
+ * milliseconds and launch counts per kernel kind: index 0 = Euler stage,
+ * 1 = Heun stage 1, 2 = Heun stage 2, 3 = QoI finalize. Synchronises. */
+sn_status sn_plan_set_timing(sn_plan *plan, int32_t on);
+sn_status sn_plan_kernel_ms(sn_plan *plan, double ms[4], int64_t counts[4]);
+
+void sn_plan_destroy(sn_plan *plan);
+
+const char *sn_status_str(sn_status s);
+const char *sn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNRT_H */

@@ -1,0 +1,98 @@
+// sn_device.h -- data shared between the host plan and the gfx950 kernels.
+//
+// Internal to libsnrt; not part of the C ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace snk {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kWavesPerWG = 4;      // 256-thread workgroups
+constexpr int kXHalo = 2;           // halo lanes on each side of a wave's row
+constexpr int kXOut = kWave - 2 * kXHalo;  // 60 output columns per wave
+constexpr int kMaxTallies = 8;
+constexpr int kMaxRects = 4;
+constexpr int kMaxQ = 1 + kMaxTallies + 2 * kMaxRects;  // mass, absorption, out, in
+
+enum StageMode : int {
+    kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)          (Euler, Heun stage 1)
+    kAverage = 1,  // psi_out = (psi_old + psi_in + dt F(psi_in)) / 2   (Heun stage 2)
+    kQoiOnly = 2,  // QoIs of psi_in, nothing written
+};
+
+enum Bc : int { kVacuum = 0, kInflow = 1, kReflect = 2 };
+enum Side : int { kW = 0, kE = 1, kS = 2, kN = 3 };
+
+// Per-ordinate constants, computed in FP64 on the host and rounded once.
+struct alignas(16) OrdConst {
+    float cx;       // dt * xi / h
+    float cy;       // dt * eta / h
+    float w;        // quadrature weight
+    int32_t flags;  // bit 0: xi > 0, bit 1: eta > 0
+    int32_t mx;     // ordinate with xi negated
+    int32_t my;     // ordinate with eta negated
+    int32_t pad0, pad1;
+    double fx;      // w |xi|  (face QoI weight along x-faces, times h in finalize)
+    double fy;      // w |eta|
+};
+
+// Per-region constants.
+struct alignas(16) RegConst {
+    float st;       // dt * (sigma_a + sigma_s)
+    float cs;       // dt * sigma_s / (2 pi)
+    float cq;       // dt * Q
+    int32_t tally;  // absorption tally id
+    double sa;      // sigma_a (absorption QoI, FP64)
+    double pad;
+};
+
+struct StageArgs {
+    const void* psi_in;   // stage input: stencils and reflective ghosts
+    const void* psi_old;  // kAverage: psi^n at the cell (may equal psi_out)
+    void* psi_out;
+    const float* phi_in;  // [G][ny][pitch] partial scalar fluxes of psi_in
+    float* phi_out;       // [G][ny][pitch] partial scalar fluxes of psi_out
+    const OrdConst* ord;
+    const RegConst* reg;
+    const uint8_t* region;  // [ny][pitch]
+    double* qpart;          // [nq][n_wg] per-workgroup QoI partial sums
+    int64_t plane;          // ny * pitch
+    int32_t nx, ny, pitch, M;
+    int32_t G, Mg;          // ordinate groups and ordinates per group
+    int32_t ntx, nty;       // tiles along x (60 columns) and y (4 * rows_per_wave rows)
+    int32_t n_wg;
+    int32_t n_tallies, n_rects, nq;
+    int32_t bc[4];
+    float ghost[4];         // inflow value per side (0 for vacuum)
+    int32_t rect[kMaxRects][4];
+};
+
+struct FinalizeArgs {
+    const double* qpart;  // [nq][n_wg]
+    const double* scale;  // [nq]
+    double* inst;         // [nq] instantaneous QoIs of the stage input
+    double* integ;        // [nq] running time integrals
+    int32_t* flags;       // bit 0: a non-finite QoI was seen
+    double coef;          // weight of this stage in the time integral
+    int32_t n_wg, nq;
+};
+
+struct PhiInitArgs {
+    const void* psi;
+    float* phi;  // [G][ny][pitch]
+    const OrdConst* ord;
+    int64_t plane;
+    int32_t nx, ny, pitch, M, G, Mg;
+};
+
+// Launchers (defined in sn_stage.hip). dtype: 0 = f32, 1 = bf16.
+hipError_t launch_stage(int order, int mode, int dtype, int rows_per_wave,
+                        const StageArgs& a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s);
+bool supported_rows_per_wave(int rows);
+
+}  // namespace snk

@@ -1,0 +1,789 @@
+// snrt_plan.cpp -- host side of the C ABI in include/snrt.h: validation of a
+// problem statement, derived constants, device-buffer layout, and the launch
+// sequence of Euler / Heun steps (arXiv 2505.17284, Sec. 4.3, eq. eq_ODE).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sn_device.h"
+#include "snrt.h"
+
+using namespace snk;
+
+namespace {
+
+thread_local std::string g_err;
+
+sn_status fail(sn_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+sn_status hip_fail(hipError_t e, const char* what) {
+    return fail(SN_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct sn_plan {
+    // statement (copied)
+    int nx = 0, ny = 0, M = 0;
+    double h = 0;
+    std::vector<double> xi, eta, w;
+    std::vector<int32_t> mx, my;
+    std::vector<uint8_t> region;
+    std::vector<double> sa, ss, q;
+    std::vector<uint8_t> tally;
+    int n_regions = 0, n_tallies = 0, n_rects = 0;
+    int bc[4] = {0, 0, 0, 0};
+    double inflow[4] = {0, 0, 0, 0};
+    int order = 1, stepper = 0, dtype = 0;
+    double cfl = 0, t_end = 0;
+    int rects[kMaxRects][4] = {};
+
+    // derived
+    int nt = 0;
+    double dt = 0;
+    int pitch = 0;
+    int64_t plane = 0;
+    int G = 1, Mg = 1, rows = 8;
+    int ntx = 0, nty = 0, n_wg = 0, nq = 0;
+    size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
+    size_t off_phi[2] = {0, 0}, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
+           off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
+    double source = 0;  // (sum w) h^2 sum_cells Q
+    std::vector<OrdConst> ord_h;
+    std::vector<RegConst> reg_h;
+    std::vector<uint8_t> region_h;  // [ny][pitch]
+    std::vector<double> scale_h;
+
+    // device
+    char* psi[2] = {nullptr, nullptr};
+    char* scratch = nullptr;
+    bool bound = false, inited = false;
+    int64_t step = 0;
+    int cur = 0;      // buffer holding the current state
+    int phi_cur = 0;  // phi buffer holding phi of the current state
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    std::vector<int> ev_kind;
+    int ev_used = 0;
+    double kernel_ms[4] = {0, 0, 0, 0};
+    int64_t kernel_count[4] = {0, 0, 0, 0};
+
+    // graph replay
+    int graph_steps = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t graph_stream = nullptr;
+
+    template <typename P>
+    P* sp(size_t off) const { return reinterpret_cast<P*>(scratch + off); }
+};
+
+namespace {
+
+sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
+    if (!p) return fail(SN_ERR_INVALID, "problem is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nx > (1 << 20) || p->ny > (1 << 20))
+        return fail(SN_ERR_INVALID, "grid %d x %d out of range [1, 2^20]", p->nx, p->ny);
+    if (!(p->h > 0) || !std::isfinite(p->h)) return fail(SN_ERR_INVALID, "cell size h must be finite and > 0");
+    if (p->M < 1 || p->M > SN_MAX_ORDINATES)
+        return fail(SN_ERR_INVALID, "M = %d out of range [1, %d]", p->M, SN_MAX_ORDINATES);
+    if (!p->xi || !p->eta || !p->w) return fail(SN_ERR_INVALID, "quadrature arrays are NULL");
+    if (!p->region || !p->sigma_a || !p->sigma_s || !p->q || !p->tally)
+        return fail(SN_ERR_INVALID, "material arrays are NULL");
+    if (p->n_regions < 1 || p->n_regions > SN_MAX_REGIONS)
+        return fail(SN_ERR_INVALID, "n_regions = %d out of range [1, %d]", p->n_regions, SN_MAX_REGIONS);
+    if (p->n_tallies < 1 || p->n_tallies > SN_MAX_TALLIES)
+        return fail(SN_ERR_INVALID, "n_tallies = %d out of range [1, %d]", p->n_tallies, SN_MAX_TALLIES);
+    if (p->n_rects < 0 || p->n_rects > SN_MAX_RECTS)
+        return fail(SN_ERR_INVALID, "n_rects = %d out of range [0, %d]", p->n_rects, SN_MAX_RECTS);
+    if (p->n_rects > 0 && !p->rects) return fail(SN_ERR_INVALID, "rects is NULL");
+    if (p->order != 1 && p->order != 2) return fail(SN_ERR_INVALID, "order must be 1 or 2");
+    if (p->stepper != SN_EULER && p->stepper != SN_HEUN) return fail(SN_ERR_INVALID, "stepper must be Euler or Heun");
+    if (p->psi_dtype != SN_F32 && p->psi_dtype != SN_BF16) return fail(SN_ERR_INVALID, "psi_dtype must be F32 or BF16");
+    if (!(p->cfl > 0) || !std::isfinite(p->cfl)) return fail(SN_ERR_INVALID, "cfl must be finite and > 0");
+    if (!(p->t_end > 0) || !std::isfinite(p->t_end)) return fail(SN_ERR_INVALID, "t_end must be finite and > 0");
+
+    const int M = p->M;
+    double sw = 0;
+    for (int k = 0; k < M; ++k) {
+        const double a = p->xi[k], b = p->eta[k], c = p->w[k];
+        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
+            return fail(SN_ERR_INVALID, "ordinate %d is not finite", k);
+        if (c < 0) return fail(SN_ERR_INVALID, "weight %d is negative", k);
+        if (a * a + b * b > 1.0 + 1e-12) return fail(SN_ERR_INVALID, "ordinate %d is not a unit direction", k);
+        sw += c;
+    }
+    if (std::fabs(sw - kTwoPi) > 1e-10 * kTwoPi)
+        return fail(SN_ERR_INVALID, "weights sum to %.17g, not 2 pi", sw);
+
+    bool need_mx = p->bc[0] == SN_BC_REFLECT || p->bc[1] == SN_BC_REFLECT;
+    bool need_my = p->bc[2] == SN_BC_REFLECT || p->bc[3] == SN_BC_REFLECT;
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc[s] < SN_BC_VACUUM || p->bc[s] > SN_BC_REFLECT)
+            return fail(SN_ERR_INVALID, "boundary kind %d on side %d", p->bc[s], s);
+        if (!std::isfinite(p->inflow[s])) return fail(SN_ERR_INVALID, "inflow on side %d not finite", s);
+    }
+    P->mx.assign(M, 0);
+    P->my.assign(M, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int32_t* m = pass == 0 ? p->mirror_x : p->mirror_y;
+        const bool need = pass == 0 ? need_mx : need_my;
+        std::vector<int32_t>& dst = pass == 0 ? P->mx : P->my;
+        if (!m) {
+            if (need) return fail(SN_ERR_INVALID, "reflective side needs mirror_%c", pass == 0 ? 'x' : 'y');
+            for (int k = 0; k < M; ++k) dst[k] = k;
+            continue;
+        }
+        for (int k = 0; k < M; ++k) {
+            const int32_t l = m[k];
+            if (l < 0 || l >= M) return fail(SN_ERR_INVALID, "mirror index %d of ordinate %d out of range", l, k);
+            if (need) {
+                const bool ok = pass == 0 ? (p->xi[l] == -p->xi[k] && p->eta[l] == p->eta[k])
+                                          : (p->eta[l] == -p->eta[k] && p->xi[l] == p->xi[k]);
+                if (!ok || p->w[l] != p->w[k])
+                    return fail(SN_ERR_INVALID, "ordinate %d has no exact mirror partner along %c", k,
+                                pass == 0 ? 'x' : 'y');
+            }
+            dst[k] = l;
+        }
+    }
+
+    for (int r = 0; r < p->n_regions; ++r) {
+        if (!(p->sigma_a[r] >= 0) || !(p->sigma_s[r] >= 0) || !std::isfinite(p->sigma_a[r]) ||
+            !std::isfinite(p->sigma_s[r]))
+            return fail(SN_ERR_INVALID, "cross-sections of region %d must be finite and >= 0", r);
+        if (!std::isfinite(p->q[r])) return fail(SN_ERR_INVALID, "source of region %d not finite", r);
+        if (p->tally[r] >= p->n_tallies) return fail(SN_ERR_INVALID, "tally of region %d out of range", r);
+    }
+    const size_t ncell = (size_t)p->nx * p->ny;
+    for (size_t c = 0; c < ncell; ++c)
+        if (p->region[c] >= p->n_regions)
+            return fail(SN_ERR_INVALID, "region id %d of cell %zu >= n_regions", p->region[c], c);
+    for (int r = 0; r < p->n_rects; ++r) {
+        const int32_t* R = p->rects + 4 * r;
+        if (!(R[0] >= 0 && R[0] < R[2] && R[2] <= p->nx && R[1] >= 0 && R[1] < R[3] && R[3] <= p->ny))
+            return fail(SN_ERR_INVALID, "rect %d = (%d, %d, %d, %d) not a non-empty cell range", r, R[0], R[1],
+                        R[2], R[3]);
+        for (int e = 0; e < 4; ++e) P->rects[r][e] = R[e];
+    }
+
+    P->nx = p->nx;
+    P->ny = p->ny;
+    P->M = M;
+    P->h = p->h;
+    P->xi.assign(p->xi, p->xi + M);
+    P->eta.assign(p->eta, p->eta + M);
+    P->w.assign(p->w, p->w + M);
+    P->region.assign(p->region, p->region + ncell);
+    P->n_regions = p->n_regions;
+    P->sa.assign(p->sigma_a, p->sigma_a + p->n_regions);
+    P->ss.assign(p->sigma_s, p->sigma_s + p->n_regions);
+    P->q.assign(p->q, p->q + p->n_regions);
+    P->tally.assign(p->tally, p->tally + p->n_regions);
+    P->n_tallies = p->n_tallies;
+    P->n_rects = p->n_rects;
+    for (int s = 0; s < 4; ++s) {
+        P->bc[s] = p->bc[s];
+        P->inflow[s] = p->inflow[s];
+    }
+    P->order = p->order;
+    P->stepper = p->stepper;
+    P->dtype = p->psi_dtype;
+    P->cfl = p->cfl;
+    P->t_end = p->t_end;
+    return SN_OK;
+}
+
+void default_shape(const sn_plan* P, int* group_size, int* rows) {
+    // Rows per wave: 8 keeps the y-halo at 3/8 of a tile row block while the
+    // per-cell registers stay small. Ordinate groups: enough workgroups to fill
+    // 256 CUs several times over, without making the phi partials (one FP32 per
+    // cell per group, read and written each stage) a visible share of traffic.
+    *rows = P->ny >= 64 ? 8 : 4;
+    const int wg_rows = kWavesPerWG * *rows;
+    const long tiles = (long)((P->nx + kXOut - 1) / kXOut) * ((P->ny + wg_rows - 1) / wg_rows);
+    int g = 1;
+    while (g < 16 && tiles * g < 2048 && P->M / (g * 2) >= 4) g *= 2;
+    *group_size = (P->M + g - 1) / g;
+}
+
+sn_status derive(sn_plan* P, int group_size, int rows) {
+    // dt = CFL * h (Sec. 5.1.3), adjusted so that N_t dt = T (Sec. 4.3).
+    const double r = P->t_end / (P->cfl * P->h);
+    P->nt = std::max(1, (int)std::ceil(r - 1e-9));
+    P->dt = P->t_end / P->nt;
+
+    int gs = 0, rw = 0;
+    default_shape(P, &gs, &rw);
+    if (group_size > 0) gs = std::min(group_size, P->M);
+    if (rows > 0) rw = rows;
+    if (!supported_rows_per_wave(rw)) return fail(SN_ERR_UNSUPPORTED, "rows_per_wave %d not compiled", rw);
+    P->Mg = gs;
+    P->G = (P->M + gs - 1) / gs;
+    P->rows = rw;
+    P->elem = P->dtype == SN_F32 ? 4 : 2;
+    const int align_elems = (int)(64 / P->elem);
+    P->pitch = (P->nx + align_elems - 1) / align_elems * align_elems;
+    P->plane = (int64_t)P->ny * P->pitch;
+    P->ntx = (P->nx + kXOut - 1) / kXOut;
+    P->nty = (P->ny + kWavesPerWG * rw - 1) / (kWavesPerWG * rw);
+    const int64_t n_wg = (int64_t)P->ntx * P->nty * P->G;
+    if (n_wg > (int64_t)0x7fffffff) return fail(SN_ERR_UNSUPPORTED, "too many workgroups");
+    P->n_wg = (int)n_wg;
+    P->nq = 1 + P->n_tallies + 2 * P->n_rects;
+
+    P->psi_bytes = align256((size_t)P->M * (size_t)P->plane * P->elem);
+    size_t off = 0;
+    const size_t phi_bytes = align256((size_t)P->G * (size_t)P->plane * sizeof(float));
+    P->off_phi[0] = off;
+    off += phi_bytes;
+    P->off_phi[1] = off;
+    off += phi_bytes;
+    P->off_ord = off;
+    off += align256((size_t)P->M * sizeof(OrdConst));
+    P->off_reg = off;
+    off += align256((size_t)P->n_regions * sizeof(RegConst));
+    P->off_region = off;
+    off += align256((size_t)P->plane);
+    P->off_qpart = off;
+    off += align256((size_t)P->nq * P->n_wg * sizeof(double));
+    P->off_scale = off;
+    off += align256(kMaxQ * sizeof(double));
+    P->off_inst = off;
+    off += align256(kMaxQ * sizeof(double));
+    P->off_integ = off;
+    off += align256(kMaxQ * sizeof(double));
+    P->off_mass0 = off;
+    off += align256(sizeof(double));
+    P->off_flags = off;
+    off += align256(sizeof(int32_t));
+    P->scratch_bytes = off;
+
+    // Tables, computed in FP64 and rounded once.
+    P->ord_h.assign(P->M, OrdConst{});
+    for (int k = 0; k < P->M; ++k) {
+        OrdConst& o = P->ord_h[k];
+        o.cx = (float)(P->dt * P->xi[k] / P->h);
+        o.cy = (float)(P->dt * P->eta[k] / P->h);
+        o.w = (float)P->w[k];
+        o.flags = (P->xi[k] > 0 ? 1 : 0) | (P->eta[k] > 0 ? 2 : 0);
+        o.mx = P->mx[k];
+        o.my = P->my[k];
+        o.fx = P->w[k] * std::fabs(P->xi[k]);
+        o.fy = P->w[k] * std::fabs(P->eta[k]);
+    }
+    P->reg_h.assign(P->n_regions, RegConst{});
+    for (int r = 0; r < P->n_regions; ++r) {
+        RegConst& c = P->reg_h[r];
+        c.st = (float)(P->dt * (P->sa[r] + P->ss[r]));
+        c.cs = (float)(P->dt * P->ss[r] / kTwoPi);
+        c.cq = (float)(P->dt * P->q[r]);
+        c.tally = P->tally[r];
+        c.sa = P->sa[r];
+    }
+    P->region_h.assign((size_t)P->plane, 0);
+    for (int j = 0; j < P->ny; ++j)
+        std::memcpy(&P->region_h[(size_t)j * P->pitch], &P->region[(size_t)j * P->nx], P->nx);
+    const double h2 = P->h * P->h;
+    P->scale_h.assign(kMaxQ, 0.0);
+    P->scale_h[0] = h2;
+    for (int t = 0; t < P->n_tallies; ++t) P->scale_h[1 + t] = h2;
+    for (int r = 0; r < 2 * P->n_rects; ++r) P->scale_h[1 + P->n_tallies + r] = P->h;
+    double sw = 0;
+    for (int k = 0; k < P->M; ++k) sw += P->w[k];
+    double sq = 0;
+    for (size_t c = 0; c < P->region.size(); ++c) sq += P->q[P->region[c]];
+    P->source = sw * h2 * sq;
+    return SN_OK;
+}
+
+StageArgs stage_args(const sn_plan* P, int mode, const char* in, const char* old, char* out, int phi_in,
+                     int phi_out) {
+    StageArgs a{};
+    a.psi_in = in;
+    a.psi_old = old;
+    a.psi_out = out;
+    a.phi_in = P->sp<float>(P->off_phi[phi_in]);
+    a.phi_out = P->sp<float>(P->off_phi[phi_out]);
+    a.ord = P->sp<OrdConst>(P->off_ord);
+    a.reg = P->sp<RegConst>(P->off_reg);
+    a.region = P->sp<uint8_t>(P->off_region);
+    a.qpart = P->sp<double>(P->off_qpart);
+    a.plane = P->plane;
+    a.nx = P->nx;
+    a.ny = P->ny;
+    a.pitch = P->pitch;
+    a.M = P->M;
+    a.G = P->G;
+    a.Mg = P->Mg;
+    a.ntx = P->ntx;
+    a.nty = P->nty;
+    a.n_wg = P->n_wg;
+    a.n_tallies = P->n_tallies;
+    a.n_rects = P->n_rects;
+    a.nq = P->nq;
+    for (int s = 0; s < 4; ++s) {
+        a.bc[s] = P->bc[s];
+        a.ghost[s] = P->bc[s] == SN_BC_INFLOW ? (float)P->inflow[s] : 0.0f;
+    }
+    for (int r = 0; r < P->n_rects; ++r)
+        for (int e = 0; e < 4; ++e) a.rect[r][e] = P->rects[r][e];
+    (void)mode;
+    return a;
+}
+
+sn_status flush_events(sn_plan* P) {
+    for (int e = 0; e < P->ev_used; ++e) {
+        HIP_TRY(hipEventSynchronize(P->ev_stop[e]), "hipEventSynchronize");
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, P->ev_start[e], P->ev_stop[e]), "hipEventElapsedTime");
+        P->kernel_ms[P->ev_kind[e]] += ms;
+        P->kernel_count[P->ev_kind[e]] += 1;
+    }
+    P->ev_used = 0;
+    return SN_OK;
+}
+
+// Launch one stage kernel and its QoI finalize. kind: 0 Euler, 1 Heun-1,
+// 2 Heun-2, -1 QoI only.
+sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timing) {
+    int mode = kind == 2 ? kAverage : (kind < 0 ? kQoiOnly : kUpdate);
+    const char* in = P->psi[P->cur];
+    char* out = P->psi[P->cur ^ 1];
+    const char* old = nullptr;
+    if (kind == 2) {  // Heun stage 2: reads psi^(1) in B, psi^n in A, writes A
+        in = P->psi[1];
+        old = P->psi[0];
+        out = P->psi[0];
+    }
+    if (kind < 0) out = nullptr;
+    StageArgs a = stage_args(P, mode, in, old, out, P->phi_cur, P->phi_cur ^ 1);
+    const bool timed = P->timing && allow_timing && kind >= 0;
+    if (timed) {
+        if (P->ev_used == (int)P->ev_start.size()) {
+            sn_status st = flush_events(P);
+            if (st != SN_OK) return st;
+        }
+        HIP_TRY(hipEventRecord(P->ev_start[P->ev_used], s), "hipEventRecord");
+    }
+    HIP_TRY(launch_stage(P->order, mode, P->dtype, P->rows, a, s), "stage launch");
+    if (timed) {
+        HIP_TRY(hipEventRecord(P->ev_stop[P->ev_used], s), "hipEventRecord");
+        P->ev_kind[P->ev_used] = kind;
+        P->ev_used++;
+    }
+    FinalizeArgs f{};
+    f.qpart = P->sp<double>(P->off_qpart);
+    f.scale = P->sp<double>(P->off_scale);
+    f.inst = P->sp<double>(P->off_inst);
+    f.integ = P->sp<double>(P->off_integ);
+    f.flags = P->sp<int32_t>(P->off_flags);
+    f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
+    f.n_wg = P->n_wg;
+    f.nq = P->nq;
+    HIP_TRY(launch_finalize(f, s), "finalize launch");
+    return SN_OK;
+}
+
+sn_status launch_steps(sn_plan* P, int n, hipStream_t s, bool allow_timing) {
+    for (int it = 0; it < n; ++it) {
+        sn_status st;
+        if (P->stepper == SN_EULER) {
+            st = launch_stage_pair(P, 0, s, allow_timing);
+            if (st != SN_OK) return st;
+            P->cur ^= 1;
+            P->phi_cur ^= 1;
+        } else {
+            st = launch_stage_pair(P, 1, s, allow_timing);
+            if (st != SN_OK) return st;
+            P->phi_cur ^= 1;
+            st = launch_stage_pair(P, 2, s, allow_timing);
+            if (st != SN_OK) return st;
+            P->phi_cur ^= 1;
+        }
+        P->step++;
+    }
+    return SN_OK;
+}
+
+void drop_graph(sn_plan* P) {
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->graph_exec = nullptr;
+    P->graph = nullptr;
+}
+
+sn_status run_steps(sn_plan* P, int n, hipStream_t s) {
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    if (n <= 0) return SN_OK;
+    int done = 0;
+    if (P->graph_steps > 0 && !P->timing) {
+        const int K = P->graph_steps;
+        // the graph covers K steps and starts from buffer/phi parity 0
+        if (n >= K && P->cur == 0 && P->phi_cur == 0) {
+            if (!P->graph_exec) {
+                hipStream_t cs;
+                HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+                HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+                const int64_t step0 = P->step;
+                sn_status st = launch_steps(P, K, cs, false);
+                P->step = step0;
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(cs, &g);
+                (void)hipStreamDestroy(cs);
+                if (st != SN_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return st;
+                }
+                if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+                P->graph = g;
+                HIP_TRY(hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+            }
+            while (n - done >= K) {
+                HIP_TRY(hipGraphLaunch(P->graph_exec, s), "hipGraphLaunch");
+                P->step += K;
+                done += K;
+            }
+        }
+    }
+    return launch_steps(P, n - done, s, true);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sn_last_error(void) { return g_err.c_str(); }
+
+const char* sn_status_str(sn_status s) {
+    switch (s) {
+    case SN_OK: return "ok";
+    case SN_ERR_INVALID: return "invalid argument";
+    case SN_ERR_OOM: return "out of memory";
+    case SN_ERR_DEVICE: return "device error";
+    case SN_ERR_UNSUPPORTED: return "unsupported";
+    case SN_ERR_NONFINITE: return "non-finite QoI";
+    case SN_ERR_BUSY: return "over budget";
+    case SN_ERR_STATE: return "bad call order";
+    default: return "unknown status";
+    }
+}
+
+sn_status sn_plan_create_tuned(const sn_problem* problem, int32_t group_size, int32_t rows_per_wave,
+                               sn_plan** out) {
+    if (!out) return fail(SN_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (group_size < 0 || rows_per_wave < 0) return fail(SN_ERR_INVALID, "negative launch shape");
+    sn_plan* P = new (std::nothrow) sn_plan();
+    if (!P) return fail(SN_ERR_OOM, "plan allocation failed");
+    sn_status st;
+    try {
+        st = validate_and_copy(problem, P);
+        if (st == SN_OK) st = derive(P, group_size, rows_per_wave);
+    } catch (const std::bad_alloc&) {
+        st = fail(SN_ERR_OOM, "host allocation failed");
+    }
+    if (st != SN_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return SN_OK;
+}
+
+sn_status sn_plan_create(const sn_problem* problem, sn_plan** out) {
+    return sn_plan_create_tuned(problem, 0, 0, out);
+}
+
+sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
+    if (!P || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    out->n_steps = P->nt;
+    out->dt = P->dt;
+    out->nx = P->nx;
+    out->ny = P->ny;
+    out->M = P->M;
+    out->pitch = P->pitch;
+    out->n_groups = P->G;
+    out->group_size = P->Mg;
+    out->rows_per_wave = P->rows;
+    out->n_workgroups = P->n_wg;
+    out->psi_bytes = P->psi_bytes;
+    out->scratch_bytes = P->scratch_bytes;
+    out->psi_dtype = P->dtype;
+    out->step = (int32_t)P->step;
+    return SN_OK;
+}
+
+sn_status sn_plan_bind(sn_plan* P, void* psi_a, void* psi_b, void* scratch) {
+    if (!P || !psi_a || !psi_b || !scratch) return fail(SN_ERR_INVALID, "NULL argument");
+    const uintptr_t pa = (uintptr_t)psi_a, pb = (uintptr_t)psi_b, ps = (uintptr_t)scratch;
+    if ((pa | pb | ps) & 255) return fail(SN_ERR_INVALID, "device buffers must be 256-byte aligned");
+    auto overlap = [](uintptr_t a, size_t na, uintptr_t b, size_t nb) { return a < b + nb && b < a + na; };
+    if (overlap(pa, P->psi_bytes, pb, P->psi_bytes) || overlap(pa, P->psi_bytes, ps, P->scratch_bytes) ||
+        overlap(pb, P->psi_bytes, ps, P->scratch_bytes))
+        return fail(SN_ERR_INVALID, "device buffers overlap");
+    drop_graph(P);
+    P->psi[0] = (char*)psi_a;
+    P->psi[1] = (char*)psi_b;
+    P->scratch = (char*)scratch;
+    P->bound = true;
+    P->inited = false;
+    return SN_OK;
+}
+
+sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
+    if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
+    if (!P->bound) return fail(SN_ERR_STATE, "plan not bound");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_ord), P->ord_h.data(), P->M * sizeof(OrdConst),
+                           hipMemcpyHostToDevice, s), "upload ordinates");
+    HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_reg), P->reg_h.data(), P->n_regions * sizeof(RegConst),
+                           hipMemcpyHostToDevice, s), "upload regions");
+    HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_region), P->region_h.data(), P->region_h.size(),
+                           hipMemcpyHostToDevice, s), "upload region map");
+    HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_scale), P->scale_h.data(), kMaxQ * sizeof(double),
+                           hipMemcpyHostToDevice, s), "upload scales");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_integ), 0, kMaxQ * sizeof(double), s), "clear integrals");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_inst), 0, kMaxQ * sizeof(double), s), "clear QoIs");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_flags), 0, sizeof(int32_t), s), "clear flags");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_phi[0]), 0, P->off_phi[1] - P->off_phi[0], s), "clear phi");
+    HIP_TRY(hipMemsetAsync(P->psi[0], 0, P->psi_bytes, s), "clear psi A");
+    HIP_TRY(hipMemsetAsync(P->psi[1], 0, P->psi_bytes, s), "clear psi B");
+    P->cur = 0;
+    P->phi_cur = 0;
+    P->step = 0;
+    drop_graph(P);
+    if (psi0) {
+        const size_t rows = (size_t)P->M * P->ny;
+        if (P->dtype == SN_F32) {
+            HIP_TRY(hipMemcpy2DAsync(P->psi[0], P->pitch * sizeof(float), psi0, P->nx * sizeof(float),
+                                     P->nx * sizeof(float), rows, hipMemcpyHostToDevice, s), "upload psi0");
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        } else {
+            std::vector<uint16_t> tmp;
+            try {
+                tmp.resize(rows * P->nx);
+            } catch (const std::bad_alloc&) {
+                return fail(SN_ERR_OOM, "host staging for psi0");
+            }
+            for (size_t e = 0; e < tmp.size(); ++e) {
+                uint32_t u;
+                std::memcpy(&u, &psi0[e], 4);
+                if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+                    u = (u >> 16) | 0x40u;
+                else
+                    u = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+                tmp[e] = (uint16_t)u;
+            }
+            HIP_TRY(hipMemcpy2DAsync(P->psi[0], P->pitch * 2, tmp.data(), P->nx * 2, P->nx * 2, rows,
+                                     hipMemcpyHostToDevice, s), "upload psi0");
+            HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
+        PhiInitArgs pa{};
+        pa.psi = P->psi[0];
+        pa.phi = P->sp<float>(P->off_phi[0]);
+        pa.ord = P->sp<OrdConst>(P->off_ord);
+        pa.plane = P->plane;
+        pa.nx = P->nx;
+        pa.ny = P->ny;
+        pa.pitch = P->pitch;
+        pa.M = P->M;
+        pa.G = P->G;
+        pa.Mg = P->Mg;
+        HIP_TRY(launch_phi_init(P->dtype, pa, s), "phi init launch");
+    }
+    // QoIs of the initial state: keep mass(0) for the balance residual.
+    P->inited = true;
+    sn_status st = launch_stage_pair(P, -1, s, false);
+    if (st != SN_OK) return st;
+    HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_mass0), P->sp<char>(P->off_inst), sizeof(double),
+                           hipMemcpyDeviceToDevice, s), "save mass0");
+    return SN_OK;
+}
+
+sn_status sn_plan_run(sn_plan* P, int32_t n_steps, void* stream) {
+    if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
+    if (n_steps < 0) return fail(SN_ERR_INVALID, "n_steps < 0");
+    const int64_t left = P->nt - P->step;
+    const int n = (int)std::min<int64_t>(n_steps, std::max<int64_t>(left, 0));
+    return run_steps(P, n, (hipStream_t)stream);
+}
+
+sn_status sn_plan_run_unbounded(sn_plan* P, int32_t n_steps, void* stream) {
+    if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
+    if (n_steps < 0) return fail(SN_ERR_INVALID, "n_steps < 0");
+    return run_steps(P, n_steps, (hipStream_t)stream);
+}
+
+sn_status sn_plan_qoi(sn_plan* P, sn_qoi* out, void* stream) {
+    if (!P || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    hipStream_t s = (hipStream_t)stream;
+    sn_status st = launch_stage_pair(P, -1, s, false);
+    if (st != SN_OK) return st;
+    double inst[kMaxQ], integ[kMaxQ], mass0 = 0;
+    int32_t flags = 0;
+    HIP_TRY(hipMemcpyAsync(inst, P->sp<char>(P->off_inst), sizeof inst, hipMemcpyDeviceToHost, s), "read QoIs");
+    HIP_TRY(hipMemcpyAsync(integ, P->sp<char>(P->off_integ), sizeof integ, hipMemcpyDeviceToHost, s),
+            "read integrals");
+    HIP_TRY(hipMemcpyAsync(&mass0, P->sp<char>(P->off_mass0), sizeof mass0, hipMemcpyDeviceToHost, s),
+            "read mass0");
+    HIP_TRY(hipMemcpyAsync(&flags, P->sp<char>(P->off_flags), sizeof flags, hipMemcpyDeviceToHost, s),
+            "read flags");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::memset(out, 0, sizeof *out);
+    const int T = P->n_tallies, R = P->n_rects;
+    out->step = P->step;
+    out->t = P->step * P->dt;
+    out->n_tallies = T;
+    out->n_rects = R;
+    out->mass = inst[0];
+    out->source = P->source;
+    out->int_mass = integ[0];
+    out->int_source = P->source * out->t;
+    double sum_abs = 0;
+    for (int t = 0; t < T; ++t) {
+        out->absorption[t] = inst[1 + t];
+        out->int_absorption[t] = integ[1 + t];
+        sum_abs += integ[1 + t];
+    }
+    for (int r = 0; r < R; ++r) {
+        out->outflow[r] = inst[1 + T + r];
+        out->inflow[r] = inst[1 + T + R + r];
+        out->int_outflow[r] = integ[1 + T + r];
+        out->int_inflow[r] = integ[1 + T + R + r];
+    }
+    const bool domain_rect =
+        R > 0 && P->rects[0][0] == 0 && P->rects[0][1] == 0 && P->rects[0][2] == P->nx && P->rects[0][3] == P->ny;
+    if (domain_rect) {
+        out->balance_residual =
+            out->mass - (mass0 + out->int_source + out->int_inflow[0] - out->int_outflow[0] - sum_abs);
+    } else {
+        out->balance_residual = 0.0;
+    }
+    bool nonfinite = flags != 0;
+    for (int e = 0; e < P->nq; ++e) nonfinite = nonfinite || !std::isfinite(inst[e]) || !std::isfinite(integ[e]);
+    out->nonfinite = nonfinite ? 1 : 0;
+    if (nonfinite) return fail(SN_ERR_NONFINITE, "a QoI is NaN or infinite at step %lld", (long long)P->step);
+    return SN_OK;
+}
+
+sn_status sn_plan_read_psi(const sn_plan* P, float* host_out, void* stream) {
+    if (!P || !host_out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t rows = (size_t)P->M * P->ny;
+    if (P->dtype == SN_F32) {
+        HIP_TRY(hipMemcpy2DAsync(host_out, P->nx * sizeof(float), P->psi[P->cur], P->pitch * sizeof(float),
+                                 P->nx * sizeof(float), rows, hipMemcpyDeviceToHost, s), "read psi");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    } else {
+        std::vector<uint16_t> tmp(rows * P->nx);
+        HIP_TRY(hipMemcpy2DAsync(tmp.data(), P->nx * 2, P->psi[P->cur], P->pitch * 2, P->nx * 2, rows,
+                                 hipMemcpyDeviceToHost, s), "read psi");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        for (size_t e = 0; e < tmp.size(); ++e) {
+            uint32_t u = (uint32_t)tmp[e] << 16;
+            std::memcpy(&host_out[e], &u, 4);
+        }
+    }
+    return SN_OK;
+}
+
+sn_status sn_plan_read_phi(const sn_plan* P, float* host_out, void* stream) {
+    if (!P || !host_out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> tmp((size_t)P->G * P->plane);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), P->sp<char>(P->off_phi[P->phi_cur]), tmp.size() * sizeof(float),
+                           hipMemcpyDeviceToHost, s), "read phi");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int j = 0; j < P->ny; ++j)
+        for (int i = 0; i < P->nx; ++i) {
+            float acc = 0.0f;
+            for (int g = 0; g < P->G; ++g) acc += tmp[(size_t)g * P->plane + (size_t)j * P->pitch + i];
+            host_out[(size_t)j * P->nx + i] = acc;
+        }
+    return SN_OK;
+}
+
+sn_status sn_plan_use_graph(sn_plan* P, int32_t steps_per_graph) {
+    if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
+    if (steps_per_graph < 0 || steps_per_graph == 1 || (steps_per_graph & 1))
+        return fail(SN_ERR_INVALID, "steps_per_graph must be 0 or an even number >= 2");
+    drop_graph(P);
+    P->graph_steps = steps_per_graph;
+    return SN_OK;
+}
+
+sn_status sn_plan_set_timing(sn_plan* P, int32_t on) {
+    if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
+    if (on && P->ev_start.empty()) {
+        const int cap = 512;
+        P->ev_start.resize(cap);
+        P->ev_stop.resize(cap);
+        P->ev_kind.resize(cap);
+        for (int e = 0; e < cap; ++e) {
+            HIP_TRY(hipEventCreate(&P->ev_start[e]), "hipEventCreate");
+            HIP_TRY(hipEventCreate(&P->ev_stop[e]), "hipEventCreate");
+        }
+    }
+    if (!on) {
+        sn_status st = flush_events(P);
+        if (st != SN_OK) return st;
+    }
+    P->timing = on != 0;
+    for (int k = 0; k < 4; ++k) {
+        P->kernel_ms[k] = 0;
+        P->kernel_count[k] = 0;
+    }
+    return SN_OK;
+}
+
+sn_status sn_plan_kernel_ms(sn_plan* P, double ms[4], int64_t counts[4]) {
+    if (!P || !ms || !counts) return fail(SN_ERR_INVALID, "NULL argument");
+    sn_status st = flush_events(P);
+    if (st != SN_OK) return st;
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = P->kernel_ms[k];
+        counts[k] = P->kernel_count[k];
+    }
+    return SN_OK;
+}
+
+void sn_plan_destroy(sn_plan* P) {
+    if (!P) return;
+    drop_graph(P);
+    for (auto e : P->ev_start) (void)hipEventDestroy(e);
+    for (auto e : P->ev_stop) (void)hipEventDestroy(e);
+    delete P;
+}
+
+}  // extern "C"

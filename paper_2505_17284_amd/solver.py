@@ -1,0 +1,167 @@
+"""Per-solve driver: one plan, device buffers from PyTorch, the HIP library does the work.
+
+    from paper_2505_17284_amd import inputs, solver
+    r = solver.solve(inputs.config(2))      # QoIs of the 700^2 lattice, 256 ordinates
+
+PyTorch only allocates device memory and supplies the stream; every stage of
+the transport step runs in libsnrt's kernels (include/snrt.h).
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (MAX_RECTS, MAX_TALLIES, SN_ERR_NONFINITE, MarshalledProblem, SnError,
+                   SnPlanInfo, SnQoi, check, lib)
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("the S_N transport library needs a ROCm GPU (torch.cuda is not available)")
+    return torch
+
+
+def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0) -> dict:
+    """Derived constants and buffer sizes of a plan (host only, no GPU)."""
+    m = MarshalledProblem(problem)
+    h = ctypes.c_void_p()
+    check(lib().sn_plan_create_tuned(ctypes.byref(m.struct), group_size, rows_per_wave,
+                                     ctypes.byref(h)), "sn_plan_create")
+    try:
+        info = SnPlanInfo()
+        check(lib().sn_plan_get_info(h, ctypes.byref(info)), "sn_plan_get_info")
+        return {f: getattr(info, f) for f, _ in SnPlanInfo._fields_}
+    finally:
+        lib().sn_plan_destroy(h)
+
+
+def qoi_dicts(problem, q: SnQoi):
+    """(instantaneous, integrated) QoIs keyed like the oracle's names."""
+    T, R = problem.n_tallies, problem.n_rects
+    inst = {"mass": q.mass, "source": q.source}
+    integ = {"mass": q.int_mass, "source": q.int_source}
+    for t in range(T):
+        inst[f"abs:{problem.tally_names[t]}"] = q.absorption[t]
+        integ[f"abs:{problem.tally_names[t]}"] = q.int_absorption[t]
+    for r in range(R):
+        inst[f"out:{problem.rect_names[r]}"] = q.outflow[r]
+        inst[f"in:{problem.rect_names[r]}"] = q.inflow[r]
+        integ[f"out:{problem.rect_names[r]}"] = q.int_outflow[r]
+        integ[f"in:{problem.rect_names[r]}"] = q.int_inflow[r]
+    return inst, integ
+
+
+class Plan:
+    """A bound, initialised solve on one GPU."""
+
+    def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, device: str = "cuda:0",
+                 psi0=None, graph_steps: int = 0):
+        torch = _torch()
+        assert problem.n_tallies <= MAX_TALLIES and problem.n_rects <= MAX_RECTS
+        self.problem = problem
+        self.device = torch.device(device)
+        self._m = MarshalledProblem(problem)
+        self.h = ctypes.c_void_p()
+        check(lib().sn_plan_create_tuned(ctypes.byref(self._m.struct), group_size, rows_per_wave,
+                                         ctypes.byref(self.h)), "sn_plan_create")
+        info = SnPlanInfo()
+        check(lib().sn_plan_get_info(self.h, ctypes.byref(info)), "sn_plan_get_info")
+        self.info = {f: getattr(info, f) for f, _ in SnPlanInfo._fields_}
+        with torch.cuda.device(self.device):
+            self.psi_a = torch.empty(int(info.psi_bytes), dtype=torch.uint8, device=self.device)
+            self.psi_b = torch.empty(int(info.psi_bytes), dtype=torch.uint8, device=self.device)
+            self.scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device=self.device)
+        check(lib().sn_plan_bind(self.h, self.psi_a.data_ptr(), self.psi_b.data_ptr(),
+                                 self.scratch.data_ptr()), "sn_plan_bind")
+        if graph_steps:
+            check(lib().sn_plan_use_graph(self.h, int(graph_steps)), "sn_plan_use_graph")
+        self.init(psi0)
+
+    @property
+    def stream(self) -> int:
+        torch = _torch()
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.info["n_steps"])
+
+    @property
+    def dt(self) -> float:
+        return float(self.info["dt"])
+
+    def init(self, psi0=None):
+        buf = None
+        if psi0 is not None:
+            buf = np.ascontiguousarray(np.asarray(psi0, dtype=np.float32).reshape(
+                self.problem.M, self.problem.ny, self.problem.nx))
+        ptr = buf.ctypes.data if buf is not None else None
+        check(lib().sn_plan_init(self.h, ptr, self.stream), "sn_plan_init")
+
+    def run(self, n_steps: int | None = None, unbounded: bool = False):
+        n = self.n_steps if n_steps is None else int(n_steps)
+        fn = lib().sn_plan_run_unbounded if unbounded else lib().sn_plan_run
+        check(fn(self.h, n, self.stream), "sn_plan_run")
+
+    def qoi(self, allow_nonfinite: bool = False):
+        q = SnQoi()
+        st = lib().sn_plan_qoi(self.h, ctypes.byref(q), self.stream)
+        if not (allow_nonfinite and st == SN_ERR_NONFINITE):
+            check(st, "sn_plan_qoi")
+        inst, integ = qoi_dicts(self.problem, q)
+        return dict(step=int(q.step), t=float(q.t), qoi=inst, qoi_int=integ,
+                    balance_residual=float(q.balance_residual), nonfinite=bool(q.nonfinite))
+
+    def psi(self) -> np.ndarray:
+        p = self.problem
+        out = np.empty((p.M, p.ny, p.nx), dtype=np.float32)
+        check(lib().sn_plan_read_psi(self.h, out.ctypes.data, self.stream), "sn_plan_read_psi")
+        return out
+
+    def phi(self) -> np.ndarray:
+        p = self.problem
+        out = np.empty((p.ny, p.nx), dtype=np.float32)
+        check(lib().sn_plan_read_phi(self.h, out.ctypes.data, self.stream), "sn_plan_read_phi")
+        return out
+
+    def set_timing(self, on: bool):
+        check(lib().sn_plan_set_timing(self.h, 1 if on else 0), "sn_plan_set_timing")
+
+    def kernel_ms(self):
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        check(lib().sn_plan_kernel_ms(self.h, ctypes.byref(ms), ctypes.byref(cnt)), "sn_plan_kernel_ms")
+        return list(ms), list(cnt)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().sn_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(problem, steps: int | None = None, psi0=None, return_psi: bool = False, **plan_kw):
+    """Run a problem to t_end (or ``steps`` steps) on the GPU and return its QoIs."""
+    plan = Plan(problem, psi0=psi0, **plan_kw)
+    try:
+        plan.run(steps)
+        r = plan.qoi()
+        r["nt"], r["dt"] = plan.n_steps, plan.dt
+        if return_psi:
+            r["psi"] = plan.psi()
+            r["phi"] = plan.phi()
+        return r
+    finally:
+        plan.close()
+
+
+__all__ = ["Plan", "solve", "plan_info", "qoi_dicts", "SnError"]

@@ -1,0 +1,75 @@
+"""Comparison helpers for GPU-vs-oracle parity tests.
+
+Tolerances (derivation in the design notes):
+  * QoIs: 1e-5 relative, the FP32 target. The outflow and the inflow through
+    a rectangle are the two halves of the gross current through its boundary,
+    and FP32 resolves each half relative to that gross current (the traces of
+    both directions carry the same absolute rounding), so out:r and in:r are
+    held to 1e-5 of out:r + in:r. QoIs below 1e-6 of the problem's scale
+    (total particles injected or present) are held to 1e-5 of that floor in
+    absolute terms instead.
+  * fields after n stages: |gpu - oracle| <= FIELD_RTOL |oracle| + atol with
+    atol = FIELD_ATOL(n) * max|oracle|: FP32 rounding of each stage's update
+    is a few ulps of the largest value in the stencil and accumulates at most
+    linearly with the number of stages.
+"""
+
+import numpy as np
+
+QOI_RTOL = 1e-5
+QOI_FLOOR = 1e-6
+FIELD_RTOL = 1e-5
+
+
+def field_atol(stages: int) -> float:
+    return 2e-7 * (stages + 2)
+
+
+def qoi_scale(inst: dict, integ: dict) -> tuple:
+    s_int = abs(integ.get("source", 0.0)) + sum(abs(v) for k, v in integ.items() if k.startswith("in:"))
+    s_int = max(s_int, abs(integ.get("mass", 0.0)), 1e-300)
+    s_inst = max(max(abs(v) for v in inst.values()), 1e-300)
+    return s_inst, s_int
+
+
+def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rtol: float = QOI_RTOL):
+    """Returns (ok, report) comparing every named QoI."""
+    s_inst, s_int = qoi_scale(orc_inst, orc_int)
+    ok = True
+    lines = []
+    for kind, g, o, scale in (("inst", gpu_inst, orc_inst, s_inst), ("int", gpu_int, orc_int, s_int)):
+        for name in o:
+            if name not in g:
+                continue
+            ov, gv = float(o[name]), float(g[name])
+            floor = QOI_FLOOR * scale
+            err = abs(gv - ov)
+            ref = abs(ov)
+            if name.startswith("out:") or name.startswith("in:"):
+                r = name.split(":", 1)[1]
+                ref = abs(float(o.get("out:" + r, 0.0))) + abs(float(o.get("in:" + r, 0.0)))
+            if ref >= floor:
+                rel = err / ref
+                good = rel <= rtol
+                tag = "" if ref == abs(ov) else " (of gross current)"
+                lines.append(f"{kind:4s} {name:14s} orc={ov:.12g} gpu={gv:.12g} rel={rel:.2e}{tag}{'' if good else '  FAIL'}")
+            else:
+                good = err <= rtol * floor
+                lines.append(f"{kind:4s} {name:14s} orc={ov:.6g} gpu={gv:.6g} abs={err:.2e} (below floor {floor:.2e}){'' if good else '  FAIL'}")
+            ok = ok and good
+    return ok, "\n".join(lines)
+
+
+def compare_field(gpu: np.ndarray, orc: np.ndarray, stages: int, rtol: float = FIELD_RTOL, atol_scale=None):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    orc = np.asarray(orc, dtype=np.float64)
+    assert gpu.shape == orc.shape, (gpu.shape, orc.shape)
+    peak = max(float(np.abs(orc).max()), 1e-300)
+    atol = (field_atol(stages) if atol_scale is None else atol_scale) * peak
+    err = np.abs(gpu - orc)
+    bad = err > rtol * np.abs(orc) + atol
+    worst = np.unravel_index(int(np.argmax(err - rtol * np.abs(orc))), err.shape)
+    rep = (f"max|err|={err.max():.3e} (peak {peak:.3e}, atol {atol:.2e}), "
+           f"bad={int(bad.sum())}/{bad.size}, worst at {tuple(int(x) for x in worst)}: "
+           f"gpu={gpu[worst]:.9g} orc={orc[worst]:.9g}")
+    return not bad.any(), rep

@@ -1,0 +1,141 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and validates problem statements on the host."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2505_17284_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2505_17284_amd import build
+
+        build.build()
+    return _lib
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "snrt.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sn_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 15
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in snrt.h but not exported"
+    assert sorted(L.EXPORTED) == names
+
+
+def test_status_strings(L):
+    lib = L.lib()
+    for s in range(8):
+        assert lib.sn_status_str(s)
+
+
+def _create(L, p, **kw):
+    m = L.MarshalledProblem(p)
+    for k, v in kw.items():
+        setattr(m.struct, k, v)
+    h = ctypes.c_void_p()
+    st = L.lib().sn_plan_create(ctypes.byref(m.struct), ctypes.byref(h))
+    if st == 0:
+        L.lib().sn_plan_destroy(h)
+    return st, L.lib().sn_last_error().decode()
+
+
+def test_valid_problems_accepted(L):
+    for p in (I.config(1), I.config(2), I.config(3), I.uq_instance(0), I.beam(), I.homogeneous()):
+        st, msg = _create(L, p)
+        assert st == 0, msg
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("cfl", 0.0, "cfl"), ("cfl", float("nan"), "cfl"), ("t_end", -1.0, "t_end"),
+    ("h", 0.0, "cell size"), ("nx", 0, "grid"), ("order", 3, "order"), ("stepper", 2, "stepper"),
+    ("n_tallies", 9, "n_tallies"), ("n_rects", 5, "n_rects"), ("psi_dtype", 7, "psi_dtype"),
+    ("M", 0, "M ="), ("n_regions", 0, "n_regions"),
+])
+def test_invalid_statements_rejected(L, field, value, needle):
+    st, msg = _create(L, I.config(1), **{field: value})
+    assert st == L.SN_ERR_INVALID and needle in msg, msg
+
+
+def test_semantic_rejections(L):
+    p = I.config(1)
+    bad_w = p.quad.w.copy() * 1.001
+    q = I.Quadrature(p.quad.mu, p.quad.xi, p.quad.eta, bad_w, p.quad.mirror_x, p.quad.mirror_y, 4, 8)
+    st, msg = _create(L, p.replace(quad=q))
+    assert st == L.SN_ERR_INVALID and "2 pi" in msg
+    # reflective walls need exact mirror partners
+    mx = p.quad.mirror_x.copy()
+    mx[0], mx[1] = mx[1], mx[0]
+    q2 = I.Quadrature(p.quad.mu, p.quad.xi, p.quad.eta, p.quad.w, mx, p.quad.mirror_y, 4, 8)
+    st, msg = _create(L, p.replace(quad=q2, bc=(I.BC_REFLECT,) * 4))
+    assert st == L.SN_ERR_INVALID and "mirror" in msg
+    st, _ = _create(L, p.replace(quad=q2))  # not needed without reflective sides
+    assert st == 0
+    reg = p.region.copy()
+    reg[3, 4] = 7
+    st, msg = _create(L, p.replace(region=reg))
+    assert st == L.SN_ERR_INVALID and "region id" in msg
+    st, msg = _create(L, p.replace(rects=np.array([(0, 0, 71, 70)], np.int32)))
+    assert st == L.SN_ERR_INVALID and "rect" in msg
+    st, msg = _create(L, p.replace(sigma_a=np.array([0.0, -1.0, 0.0])))
+    assert st == L.SN_ERR_INVALID and "cross-sections" in msg
+    tal = np.array([0, 1, 5], np.uint8)
+    st, msg = _create(L, p.replace(tally=tal))
+    assert st == L.SN_ERR_INVALID and "tally" in msg
+
+
+def test_time_steps_agree_with_oracle(L, orc):
+    """Library and oracle derive N_t and dt independently from (T, CFL, h)."""
+    from paper_2505_17284_amd import solver
+
+    for p in (I.config(1), I.config(2), I.config(3), I.lattice(100, 32), I.uq_instance(3),
+              I.cavity(333, 32)):
+        info = solver.plan_info(p)
+        nt, dt = orc.num_steps(p)
+        assert info["n_steps"] == nt and info["dt"] == dt, (p.name, info["n_steps"], nt)
+
+
+def test_buffer_sizes(L):
+    from paper_2505_17284_amd import solver
+
+    info = solver.plan_info(I.config(2))
+    assert info["pitch"] >= 700 and info["pitch"] % 16 == 0
+    assert info["psi_bytes"] >= 256 * 700 * info["pitch"] * 4
+    assert info["psi_bytes"] % 256 == 0 and info["scratch_bytes"] % 256 == 0
+    bf = solver.plan_info(I.config(2).replace(psi_dtype="bf16"))
+    assert bf["psi_bytes"] < info["psi_bytes"] * 0.51
+
+
+def test_calls_in_wrong_order_fail_cleanly(L):
+    p = I.config(1)
+    m = L.MarshalledProblem(p)
+    h = ctypes.c_void_p()
+    lib = L.lib()
+    assert lib.sn_plan_create(ctypes.byref(m.struct), ctypes.byref(h)) == 0
+    try:
+        assert lib.sn_plan_run(h, 1, None) == L.SN_ERR_STATE
+        q = L.SnQoi()
+        assert lib.sn_plan_qoi(h, ctypes.byref(q), None) == L.SN_ERR_STATE
+        assert lib.sn_plan_bind(h, None, None, None) == L.SN_ERR_INVALID
+        assert lib.sn_plan_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(1024)) \
+            == L.SN_ERR_INVALID  # overlapping
+        assert lib.sn_plan_use_graph(h, 3) == L.SN_ERR_INVALID
+    finally:
+        lib.sn_plan_destroy(h)
