@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB "
+                         "(reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -134,6 +137,15 @@ def main():
         "roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / (step_bytes / problem.cell_ordinates),
     }
     plan.close()
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = n
+        del src, dst
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(line), flush=True)

@@ -109,16 +109,19 @@ typedef struct sn_problem {
 
 /* Sizes and derived constants of a plan. psi_bytes is the size of ONE angular
  * flux buffer; a plan needs two (A and B) plus one scratch buffer, each
- * 256-byte aligned. The device layout of psi is [M][ny][pitch] elements,
- * x fastest, pitch >= nx. */
+ * 256-byte aligned. Each ordinate's plane in a psi buffer holds the nx * ny
+ * cells inside a frame of two ghost cells, x fastest, rows of `pitch`
+ * elements (pitch >= nx + 4); sn_plan_read_psi returns the plain
+ * [M][ny][nx] array. */
 typedef struct sn_plan_info {
     int32_t n_steps;   /* N_t */
     double dt;
     int32_t nx, ny, M, pitch;
     int32_t n_groups;  /* ordinate groups (phi partials per cell) */
-    int32_t group_size;
-    int32_t rows_per_wave;
-    int32_t n_workgroups; /* workgroups of one stage launch */
+    int32_t group_size;      /* ordinates per workgroup */
+    int32_t rows_per_wave;   /* grid rows per wavefront */
+    int32_t waves_per_group; /* wavefronts per workgroup, stacked along y */
+    int32_t n_workgroups;    /* workgroups of one stage launch */
     uint64_t psi_bytes;
     uint64_t scratch_bytes;
     int32_t psi_dtype;
@@ -154,10 +157,13 @@ typedef struct sn_plan sn_plan;
  * sn_last_error() for a statement the method does not define. */
 sn_status sn_plan_create(const sn_problem *problem, sn_plan **out);
 
-/* Same, with explicit launch shape: group_size ordinates per workgroup and
- * rows_per_wave rows per wavefront (0 = library default). */
+/* Same, with an explicit launch shape (0 = library default for each):
+ * group_size ordinates per workgroup, rows_per_wave grid rows per wavefront
+ * (2 or 4), waves_per_group wavefronts per workgroup (4, 8 or 16). Returns
+ * SN_ERR_UNSUPPORTED for a shape the library was not compiled for. */
 sn_status sn_plan_create_tuned(const sn_problem *problem, int32_t group_size,
-                               int32_t rows_per_wave, sn_plan **out);
+                               int32_t rows_per_wave, int32_t waves_per_group,
+                               sn_plan **out);
 
 sn_status sn_plan_get_info(const sn_plan *plan, sn_plan_info *out);
 

@@ -54,7 +54,8 @@ class SnProblem(ctypes.Structure):
 class SnPlanInfo(ctypes.Structure):
     _fields_ = [
         ("n_steps", _i32), ("dt", _d), ("nx", _i32), ("ny", _i32), ("M", _i32), ("pitch", _i32),
-        ("n_groups", _i32), ("group_size", _i32), ("rows_per_wave", _i32), ("n_workgroups", _i32),
+        ("n_groups", _i32), ("group_size", _i32), ("rows_per_wave", _i32), ("waves_per_group", _i32),
+        ("n_workgroups", _i32),
         ("psi_bytes", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64), ("psi_dtype", _i32),
         ("step", _i32),
     ]
@@ -86,10 +87,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it first (paper_2505_17284_amd/build.py)")
+        # One HIP runtime per process: PyTorch, which supplies the device memory
+        # and streams, ships its own libamdhip64 with the same soname. Loading it
+        # first makes the library bind to that copy instead of a second runtime.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         PP = ctypes.POINTER(_vp)
         L.sn_plan_create.argtypes = [ctypes.POINTER(SnProblem), PP]
-        L.sn_plan_create_tuned.argtypes = [ctypes.POINTER(SnProblem), _i32, _i32, PP]
+        L.sn_plan_create_tuned.argtypes = [ctypes.POINTER(SnProblem), _i32, _i32, _i32, PP]
         L.sn_plan_get_info.argtypes = [_vp, ctypes.POINTER(SnPlanInfo)]
         L.sn_plan_bind.argtypes = [_vp, _vp, _vp, _vp]
         L.sn_plan_init.argtypes = [_vp, _vp, _vp]

@@ -1,0 +1,190 @@
+// sn_aux.hip -- the small kernels around the stage: QoI/phi finalize, the
+// ghost-frame fill of a freshly set state, phi of a given state, and the
+// launch dispatch over (order, storage type).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sn_device.h"
+#include "sn_stage_impl.h"
+
+namespace snk {
+
+template <typename T>
+__device__ __forceinline__ float ld(const T* p);
+template <>
+__device__ __forceinline__ float ld<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float ld<uint16_t>(const uint16_t* p) { return bf16_widen(*p); }
+template <typename T>
+__device__ __forceinline__ void st(T* p, float v);
+template <>
+__device__ __forceinline__ void st<float>(float* p, float v) { *p = v; }
+template <>
+__device__ __forceinline__ void st<uint16_t>(uint16_t* p, float v) { *p = (uint16_t)bf16_narrow(v); }
+
+// ---------------------------------------------------------------- ghost frame
+// Sets the ghost frame of every ordinate from the interior of the same state
+// (the rule the stage kernels maintain): an ordinate entering through a side
+// gets the side's ghost value in both layers (inflow value, 0 for vacuum, or
+// the mirror ordinate's boundary cell for a reflective side); an ordinate
+// leaving through a side gets a copy of its boundary cell in the first layer.
+// This is ordinate k's frame along row/column idx; it reads only interior
+// cells, so every (k, idx) can run concurrently. Used when a state is set
+// from outside; the stage kernels maintain the frame of what they write.
+template <typename T>
+__device__ __forceinline__ void ghost_update(const GhostArgs& a, int k, int idx) {
+    const OrdConst o = a.ord[k];
+    const bool sx = (o.flags & 1) != 0, sy = (o.flags & 2) != 0;
+    T* psi = static_cast<T*>(a.psi);
+    T* pk = psi + (int64_t)k * a.plane;
+    const T* pmx = psi + (int64_t)o.mx * a.plane;
+    const T* pmy = psi + (int64_t)o.my * a.plane;
+    const int64_t P = a.pitch;
+    const int nx = a.nx, ny = a.ny;
+    if (idx < ny) {
+        const int64_t row = (int64_t)(idx + kGhost) * P;
+        if (sx) {  // enters through W
+            const float g = a.bc[kW] == kReflect ? ld(pmx + row + kGhost) : a.ghost[kW];
+            st(pk + row + 1, g);
+            st(pk + row + 0, g);
+        } else {
+            st(pk + row + 1, ld(pk + row + kGhost));
+        }
+        if (!sx) {  // enters through E
+            const float g = a.bc[kE] == kReflect ? ld(pmx + row + kGhost + nx - 1) : a.ghost[kE];
+            st(pk + row + kGhost + nx, g);
+            st(pk + row + kGhost + nx + 1, g);
+        } else {
+            st(pk + row + kGhost + nx, ld(pk + row + kGhost + nx - 1));
+        }
+    }
+    if (idx < nx) {
+        const int64_t col = idx + kGhost;
+        if (sy) {  // enters through S
+            const float g = a.bc[kS] == kReflect ? ld(pmy + kGhost * P + col) : a.ghost[kS];
+            st(pk + 1 * P + col, g);
+            st(pk + 0 * P + col, g);
+        } else {
+            st(pk + 1 * P + col, ld(pk + kGhost * P + col));
+        }
+        if (!sy) {  // enters through N
+            const float g = a.bc[kN] == kReflect ? ld(pmy + (int64_t)(ny - 1 + kGhost) * P + col) : a.ghost[kN];
+            st(pk + (int64_t)(ny + kGhost) * P + col, g);
+            st(pk + (int64_t)(ny + kGhost + 1) * P + col, g);
+        } else {
+            st(pk + (int64_t)(ny + kGhost) * P + col, ld(pk + (int64_t)(ny - 1 + kGhost) * P + col));
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) sn_ghost_fill_kernel(const GhostArgs a) {
+    ghost_update<T>(a, blockIdx.y, blockIdx.x * 256 + threadIdx.x);
+}
+
+// ---------------------------------------------------------------- finalize
+// Workgroups [0, nq): one per QoI slot; sums the per-workgroup partials in a
+// fixed order (deterministic), scales, and accumulates the time integral.
+// Workgroups [nq, nq + n_phi_wg): phi = sum over groups of the stage's
+// partial scalar fluxes, in group order, for every interior cell.
+__global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs a) {
+    if ((int)blockIdx.x >= a.nq) {
+        const int64_t c = (int64_t)(blockIdx.x - a.nq) * 256 + threadIdx.x;
+        if (c >= (int64_t)a.nx * a.ny) return;
+        const int64_t j = c / a.nx, i = c - j * a.nx;
+        const int64_t off = (j + kGhost) * a.pitch + i + kGhost;
+        // all loads first (independent), then the sum in group order
+        float part[32];
+        const int G = a.G;
+#pragma unroll
+        for (int g = 0; g < 32; ++g)
+            if (g < G) part[g] = a.phi_part[(int64_t)g * a.plane + off];
+        float acc = part[0];
+#pragma unroll
+        for (int g = 1; g < 32; ++g)
+            if (g < G) acc += part[g];
+        for (int g = 32; g < G; ++g) acc += a.phi_part[(int64_t)g * a.plane + off];
+        a.phi[off] = acc;
+        return;
+    }
+    const int s = blockIdx.x;
+    // eight independent accumulators per thread, combined in a fixed order
+    const double* qp = a.qpart + (int64_t)s * a.n_wg;
+    double acc8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc8[u] = 0.0;
+    for (int w0 = threadIdx.x; w0 < a.n_wg; w0 += 256 * 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int w = w0 + u * 256;
+            if (w < a.n_wg) acc8[u] += qp[w];
+        }
+    }
+    double acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double tot = red[0] * a.scale[s];
+        a.inst[s] = tot;
+        a.integ[s] += a.coef * tot;
+        if (!isfinite(tot)) a.flags[0] = 1;
+    }
+}
+
+// ---------------------------------------------------------------- phi of a given state
+template <typename T>
+__global__ void __launch_bounds__(256) sn_phi_init_kernel(const PhiInitArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)a.nx * a.ny) return;
+    const int64_t j = c / a.nx, i = c - j * a.nx;
+    const int64_t off = (j + kGhost) * a.pitch + i + kGhost;
+    const T* psi = static_cast<const T*>(a.psi);
+    float acc = 0.0f;
+    for (int k = 0; k < a.M; ++k) acc = fmaf(a.ord[k].w, ld(psi + (int64_t)k * a.plane + off), acc);
+    a.phi[off] = acc;
+}
+
+// ---------------------------------------------------------------- launchers
+bool supported_shape(int rows, int waves) {
+    return (rows == 2 || rows == 4) && (waves == 4 || waves == 8 || waves == 16);
+}
+
+hipError_t launch_stage(int order, int mode, int dtype, int rows, int waves, const StageArgs& a, hipStream_t s) {
+    if (order == 1)
+        return dtype == 0 ? launch_stage_o1_f32(mode, rows, waves, a, s) : launch_stage_o1_bf16(mode, rows, waves, a, s);
+    if (order == 2)
+        return dtype == 0 ? launch_stage_o2_f32(mode, rows, waves, a, s) : launch_stage_o2_bf16(mode, rows, waves, a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq + a.n_phi_wg), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s) {
+    const int n = a.nx > a.ny ? a.nx : a.ny;
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)a.M), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(sn_ghost_fill_kernel<float>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(sn_ghost_fill_kernel<uint16_t>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s) {
+    const int64_t cells = (int64_t)a.nx * a.ny;
+    const dim3 grid((unsigned)((cells + 255) / 256)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(sn_phi_init_kernel<float>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(sn_phi_init_kernel<uint16_t>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace snk

@@ -1,6 +1,15 @@
 // sn_device.h -- data shared between the host plan and the gfx950 kernels.
 //
 // Internal to libsnrt; not part of the C ABI.
+//
+// Device layout of every per-cell plane (psi per ordinate, phi, its
+// per-group partials, the region map): [ny_alloc][pitch] elements with a
+// frame of two ghost cells on every side. Interior cell (i, j) sits at
+//     origin + j * pitch + i,    origin = 2 * pitch + 2.
+// The ghost cells of psi carry, per ordinate and side, the value that makes
+// the interior reconstruction formula produce the boundary traces of the
+// method (see sn_stage_impl.h); the stage kernels write them for the state
+// they produce.
 #pragma once
 
 #include <stdint.h>
@@ -9,16 +18,16 @@
 
 namespace snk {
 
-constexpr int kWave = 64;           // CDNA wavefront width
-constexpr int kWavesPerWG = 4;      // 256-thread workgroups
-constexpr int kXHalo = 2;           // halo lanes on each side of a wave's row
-constexpr int kXOut = kWave - 2 * kXHalo;  // 60 output columns per wave
+constexpr int kWave = 64;                      // CDNA wavefront width
+constexpr int kCellsPerLane = 2;               // consecutive x-cells held by one lane
+constexpr int kTileX = kCellsPerLane * (kWave - 2);  // 124 output columns per wave (lanes 1..62)
+constexpr int kGhost = 2;                      // ghost-frame width
 constexpr int kMaxTallies = 8;
 constexpr int kMaxRects = 4;
 constexpr int kMaxQ = 1 + kMaxTallies + 2 * kMaxRects;  // mass, absorption, out, in
 
 enum StageMode : int {
-    kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)          (Euler, Heun stage 1)
+    kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)                   (Euler, Heun stage 1)
     kAverage = 1,  // psi_out = (psi_old + psi_in + dt F(psi_in)) / 2   (Heun stage 2)
     kQoiOnly = 2,  // QoIs of psi_in, nothing written
 };
@@ -50,49 +59,69 @@ struct alignas(16) RegConst {
 };
 
 struct StageArgs {
-    const void* psi_in;   // stage input: stencils and reflective ghosts
+    const void* psi_in;   // stage input: stencils
     const void* psi_old;  // kAverage: psi^n at the cell (may equal psi_out)
     void* psi_out;
-    const float* phi_in;  // [G][ny][pitch] partial scalar fluxes of psi_in
-    float* phi_out;       // [G][ny][pitch] partial scalar fluxes of psi_out
+    const float* phi;     // scalar flux of psi_in (plane)
+    float* phi_part;      // [G] planes: per-group partial scalar fluxes of psi_out
     const OrdConst* ord;
     const RegConst* reg;
-    const uint8_t* region;  // [ny][pitch]
+    const uint8_t* region;  // plane of region ids
     double* qpart;          // [nq][n_wg] per-workgroup QoI partial sums
-    int64_t plane;          // ny * pitch
+    int64_t plane;          // ny_alloc * pitch (elements)
     int32_t nx, ny, pitch, M;
     int32_t G, Mg;          // ordinate groups and ordinates per group
-    int32_t ntx, nty;       // tiles along x (60 columns) and y (4 * rows_per_wave rows)
+    int32_t ntx, nty;       // tiles along x (124 columns) and y (waves * rows_per_wave rows)
     int32_t n_wg;
     int32_t n_tallies, n_rects, nq;
     int32_t bc[4];
-    float ghost[4];         // inflow value per side (0 for vacuum)
     int32_t rect[kMaxRects][4];
 };
 
+struct GhostArgs {
+    void* psi;
+    const OrdConst* ord;
+    int64_t plane;
+    int32_t nx, ny, pitch, M;
+    int32_t bc[4];
+    float ghost[4];  // inflow value per side (0 for vacuum)
+};
+
 struct FinalizeArgs {
-    const double* qpart;  // [nq][n_wg]
-    const double* scale;  // [nq]
-    double* inst;         // [nq] instantaneous QoIs of the stage input
-    double* integ;        // [nq] running time integrals
-    int32_t* flags;       // bit 0: a non-finite QoI was seen
-    double coef;          // weight of this stage in the time integral
+    const float* phi_part;  // [G] planes written by the stage
+    float* phi;             // their sum: phi of the stage output
+    int64_t plane;
+    int32_t nx, ny, pitch, G;
+    int32_t n_phi_wg;       // workgroups reducing phi (0: the stage wrote no partials)
+    const double* qpart;    // [nq][n_wg]
+    const double* scale;    // [nq]
+    double* inst;           // [nq] instantaneous QoIs of the stage input
+    double* integ;          // [nq] running time integrals
+    int32_t* flags;         // bit 0: a non-finite QoI was seen
+    double coef;            // weight of this stage in the time integral
     int32_t n_wg, nq;
 };
 
 struct PhiInitArgs {
     const void* psi;
-    float* phi;  // [G][ny][pitch]
+    float* phi;
     const OrdConst* ord;
     int64_t plane;
-    int32_t nx, ny, pitch, M, G, Mg;
+    int32_t nx, ny, pitch, M;
 };
 
-// Launchers (defined in sn_stage.hip). dtype: 0 = f32, 1 = bf16.
-hipError_t launch_stage(int order, int mode, int dtype, int rows_per_wave,
-                        const StageArgs& a, hipStream_t s);
+// Launchers. dtype: 0 = f32, 1 = bf16.
+hipError_t launch_stage(int order, int mode, int dtype, int rows_per_wave, int waves, const StageArgs& a,
+                        hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s);
 hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s);
-bool supported_rows_per_wave(int rows);
+bool supported_shape(int rows_per_wave, int waves);
+
+// Per translation unit (sn_stage_o{1,2}_{f32,bf16}.hip).
+hipError_t launch_stage_o1_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_o2_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_o1_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_o2_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 
 }  // namespace snk

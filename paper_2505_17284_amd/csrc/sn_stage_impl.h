@@ -1,0 +1,641 @@
+// sn_stage_impl.h -- the gfx950 stage kernel of the explicit S_N finite-volume step.
+//
+// One stage evaluates, for every ordinate k and cell (i, j) of a uniform grid
+// of square cells (arXiv 2505.17284, Sec. 4.2, eq. eq_sn_2d_eqn_fv divided by
+// the cell area h^2),
+//
+//   dt F = -(dt xi_k / h)(trace_{i+1/2} - trace_{i-1/2})
+//          -(dt eta_k / h)(trace_{j+1/2} - trace_{j-1/2})
+//          - dt sigma_t psi + dt sigma_s / (2 pi) phi + dt Q,
+//
+// with the upwind trace of eq. eq_upwind1stOrder: the upwind cell's value for
+// first order, or its minmod-limited linear reconstruction at the face for
+// second order. The stage update follows Sec. 4.3 (eq. eq_ODE): psi + dt F
+// (Euler and Heun's first stage) or (psi^n + psi^(1) + dt F(psi^(1))) / 2
+// (Heun's second stage, written in place over psi^n). The scalar flux
+// phi = sum_k w_k psi_k of the written state (Sec. 4.1) leaves as a per-group
+// epilogue, and FP64 partial sums of the QoIs of the stage input (mass,
+// absorption per tally, outflow and inflow through rectangle boundaries,
+// Sec. 3.1.2) leave per workgroup.
+//
+// Boundaries without boundary code: every psi plane carries a two-cell ghost
+// frame. For an ordinate entering through a side, both ghost layers hold the
+// ghost value of the end of Sec. 4.2 (the inflow value, 0 for vacuum, or the
+// mirror ordinate's boundary value for a reflective wall); for an ordinate
+// leaving through a side, the first ghost layer repeats the boundary cell.
+// With those values the interior formula gives exactly the method's boundary
+// traces: first order on boundary faces (the limiter sees a zero difference),
+// and the ghost value in the slope of the first interior cell. The waves that
+// write boundary cells also write the frame of the new state (write_frame);
+// incoming vacuum/inflow ghosts are constant and set once.
+//
+// Mapping: a wavefront owns 128 consecutive padded columns, two per lane
+// (lanes 1..62 produce output, lanes 0 and 63 are halo; neighbours cross
+// lanes through DPP wave shifts), and TY rows; the four waves of a workgroup
+// are stacked in y and share one LDS copy of each ordinate's rows, halo rows
+// included, while the next ordinate's rows are in flight. Per-cell material
+// data and the incoming scalar flux stay in registers across the ordinate
+// loop. Global accesses are buffer instructions: one scalar resource per
+// plane, wave-uniform row offsets, one per-lane offset.
+// There is no MFMA: the stage is a bandwidth-bound stencil.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sn_device.h"
+
+namespace snk {
+
+// ---------------------------------------------------------------- storage
+template <typename T>
+struct Store;
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
+
+// Buffer resource over `bytes` bytes from `base` (raw, untyped). Accesses whose
+// per-lane offset is at or beyond `bytes` read 0 and write nothing.
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// A per-lane byte offset that the buffer range check always rejects.
+constexpr uint32_t kDropOffset = 0x80000000u;
+
+template <>
+struct Store<float> {
+    static __device__ __forceinline__ float2 load2(const char* p) { return *reinterpret_cast<const float2*>(p); }
+    static __device__ __forceinline__ float2 round2(float2 v) { return v; }
+    static __device__ __forceinline__ void store2(char* p, float2 v) { *reinterpret_cast<float2*>(p) = v; }
+    static __device__ __forceinline__ void store1(char* p, float v) { *reinterpret_cast<float*>(p) = v; }
+    static __device__ __forceinline__ float2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void bstore2(rsrc_t r, uint32_t voff, uint32_t soff, float2 v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    }
+    static __device__ __forceinline__ void bstore1(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    }
+};
+
+// bfloat16 kept as raw 16-bit patterns: widening is exact, narrowing rounds
+// to nearest even (NaN stays NaN).
+__device__ __forceinline__ float bf16_widen(uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ uint32_t bf16_narrow(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+template <>
+struct Store<uint16_t> {
+    static __device__ __forceinline__ float2 load2(const char* p) {
+        const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
+        return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
+    }
+    static __device__ __forceinline__ float2 round2(float2 v) {
+        return make_float2(bf16_widen(bf16_narrow(v.x)), bf16_widen(bf16_narrow(v.y)));
+    }
+    // v must already be representable (round2): narrowing is then exact.
+    static __device__ __forceinline__ void store2(char* p, float2 v) {
+        *reinterpret_cast<uint32_t*>(p) = (__float_as_uint(v.x) >> 16) | (__float_as_uint(v.y) & 0xffff0000u);
+    }
+    static __device__ __forceinline__ void store1(char* p, float v) {
+        *reinterpret_cast<uint16_t*>(p) = (uint16_t)(__float_as_uint(v) >> 16);
+    }
+    static __device__ __forceinline__ float2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
+    }
+    static __device__ __forceinline__ void bstore2(rsrc_t r, uint32_t voff, uint32_t soff, float2 v) {
+        __builtin_amdgcn_raw_buffer_store_b32((__float_as_uint(v.x) >> 16) | (__float_as_uint(v.y) & 0xffff0000u), r,
+                                              voff, soff, 0);
+    }
+    static __device__ __forceinline__ void bstore1(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(__float_as_uint(v) >> 16), r, voff, soff, 0);
+    }
+};
+
+// ---------------------------------------------------------------- helpers
+// Lane l receives x from lane l-1 (lane 0 reads 0): DPP wave_shr:1. Lanes 0
+// and 63 are halo lanes whose results are never stored, so the value shifted
+// in at the wave's edge does not matter; bound_ctrl lets the move fold into
+// the instruction that consumes it.
+__device__ __forceinline__ float lane_from_left(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138, 0xf, 0xf, true));
+}
+// Lane l receives x from lane l+1 (lane 63 reads 0): DPP wave_shl:1.
+__device__ __forceinline__ float lane_from_right(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130, 0xf, 0xf, true));
+}
+
+// minmod(a, b): the argument of smaller magnitude when both have the same
+// strict sign, else 0. Exactly one of the two terms is non-zero, so the sum
+// is exact.
+__device__ __forceinline__ float minmod(float a, float b) {
+    return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+// Face-QoI tags of one cell: bit (4 * kind + q) is set when the cell's face of
+// that kind (0 W, 1 E, 2 S, 3 N) lies on the boundary of rectangle q. Each
+// rectangle-boundary face is assigned to the cell inside the rectangle.
+__device__ __forceinline__ uint32_t face_tags(const StageArgs& a, int i, int j, bool valid) {
+    uint32_t tg = 0;
+    if (!valid || j >= a.ny) return 0;
+    for (int q = 0; q < a.n_rects; ++q) {
+        const int i0 = a.rect[q][0], j0 = a.rect[q][1], i1 = a.rect[q][2], j1 = a.rect[q][3];
+        const bool rows = j >= j0 && j < j1, cols = i >= i0 && i < i1;
+        if (rows && i == i0) tg |= 1u << (0 + q);
+        if (rows && i == i1 - 1) tg |= 1u << (4 + q);
+        if (cols && j == j0) tg |= 1u << (8 + q);
+        if (cols && j == j1 - 1) tg |= 1u << (12 + q);
+    }
+    return tg;
+}
+
+// Adds w |Omega.n| trace to the lane's outflow or inflow accumulator of every
+// rectangle whose boundary holds one of the tagged faces. West face: Omega.n =
+// -xi; east: xi; south: -eta; north: eta.
+__device__ __forceinline__ void face_accumulate(uint32_t tg, float tW, float tE, float tS, float tN, double fx,
+                                                double fy, bool sx, bool sy, int n_rects, double* facc,
+                                                int nthreads) {
+#pragma unroll 1
+    while (tg) {
+        const int b = __builtin_ctz(tg);
+        tg &= tg - 1;
+        const int kind = b >> 2, q = b & 3;
+        const float tr = kind == 0 ? tW : (kind == 1 ? tE : (kind == 2 ? tS : tN));
+        const bool out = kind == 0 ? !sx : (kind == 1 ? sx : (kind == 2 ? !sy : sy));
+        const double wgt = kind < 2 ? fx : fy;
+        double* slot = facc + (out ? q : n_rects + q) * nthreads;
+        *slot = fma(wgt, (double)tr, *slot);
+    }
+}
+
+// ---------------------------------------------------------------- per-wave state
+template <int TY>
+struct WaveCtx {
+    int y0;              // interior row of the wave's first output row (wave-uniform)
+    int i0;              // interior column of the lane's first cell
+    uint32_t lane_off;   // byte offset of the lane's cell pair within a padded row
+    uint32_t store_off;  // lane_off for lanes storing a full pair, kDropOffset otherwise
+    uint32_t single_off; // lane_off for a lane owning only its first cell, kDropOffset otherwise
+    // Ghost frame of the written state (kDropOffset for lanes that own no
+    // boundary cell): byte offsets in a row of ghost columns -1, -2 (lane
+    // holding column 0) and nx, nx+1 (lane holding column nx-1).
+    uint32_t gw1, gw2, ge1, ge2;
+    bool ge_first;       // column nx-1 is the lane's first cell
+    bool ghost_wave;     // the wave holds a boundary cell (wave-uniform)
+    uint32_t pitchb;     // bytes per padded row
+    uint32_t planeb;     // bytes per plane
+    bool ragged;         // some lane of the wave owns only its first cell (wave-uniform)
+    bool v0, v1;         // the lane's cells are output cells of this wave
+    bool any_tag;        // some lane owns a rectangle-boundary face (wave-uniform)
+    float2 st[TY];       // dt sigma_t per cell
+    float2 bb[TY];       // dt (sigma_s / (2 pi) phi + Q) per cell
+    float2 phacc[TY];    // sum_k w_k psi_out over the group's ordinates
+    uint32_t tags[TY];   // face tags, cell 0 in the low half
+};
+
+// Rows of one ordinate staged in LDS for the whole workgroup: the 4 waves
+// share their halo rows, so a workgroup reads 4 TY + 4 rows per ordinate
+// instead of 4 (TY + 4). Thread (wave, lane) loads staged rows wave + 4 m.
+template <int TY, int W>
+struct RowStage {
+    static constexpr int kRows = W * TY + 4;             // staged rows per ordinate
+    static constexpr int kPer = (kRows + W - 1) / W;     // rows loaded per thread
+};
+
+template <typename T, int TY, int W>
+__device__ __forceinline__ void stage_issue(const StageArgs& a, int k, int yw, int wave, const WaveCtx<TY>& w,
+                                            float2 (&pre)[RowStage<TY, W>::kPer]) {
+    const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_in) + (size_t)k * w.planeb, w.planeb);
+#pragma unroll
+    for (int m = 0; m < RowStage<TY, W>::kPer; ++m) {
+        const int q = wave + W * m;
+        if (q < RowStage<TY, W>::kRows) pre[m] = Store<T>::bload2(r, w.lane_off, (uint32_t)(yw + q) * w.pitchb);
+    }
+}
+
+template <int TY, int W>
+__device__ __forceinline__ void stage_commit(float2 (*buf)[kWave], int wave, int lane,
+                                             const float2 (&pre)[RowStage<TY, W>::kPer]) {
+#pragma unroll
+    for (int m = 0; m < RowStage<TY, W>::kPer; ++m) {
+        const int q = wave + W * m;
+        if (q < RowStage<TY, W>::kRows) buf[q][lane] = pre[m];
+    }
+}
+
+// psi^n at the wave's own cells (Heun stage 2).
+template <typename T, int TY>
+__device__ __forceinline__ void load_old(const StageArgs& a, int k, const WaveCtx<TY>& w, float2 (&o)[TY]) {
+    const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_old) + (size_t)k * w.planeb, w.planeb);
+    const uint32_t row0 = (uint32_t)(w.y0 + kGhost) * w.pitchb;
+#pragma unroll
+    for (int t = 0; t < TY; ++t) o[t] = Store<T>::bload2(r, w.lane_off, row0 + t * w.pitchb);
+}
+
+// Stores one cell pair (or the first cell only) at byte offset `off` of plane base `p`.
+template <typename T>
+__device__ __forceinline__ void put_pair(char* p, size_t off, float2 v, bool v0, bool v1) {
+    if (v1) Store<T>::store2(p + off, v);
+    else if (v0) Store<T>::store1(p + off, v.x);
+}
+
+// Keeps the ghost frame of the written state (the rule of the header comment):
+// ordinate k leaving through a side repeats its boundary cell into the first
+// ghost layer; on a reflective side the mirror ordinate, which enters there,
+// gets the value in both layers. Lanes without a boundary cell carry the
+// dropped offset, so the stores need no branches.
+template <typename T, int TY, bool SX, bool SY>
+__device__ __forceinline__ void write_frame(const StageArgs& a, const OrdConst& o, int k, int j, uint32_t rowb,
+                                            rsrc_t rout, const WaveCtx<TY>& w, float2 v) {
+    const char* out = static_cast<const char*>(a.psi_out);
+    if (!SX) {  // leaves through W
+        Store<T>::bstore1(rout, w.gw1, rowb, v.x);
+        if (a.bc[kW] == kReflect) {
+            const rsrc_t rm = make_rsrc(out + (size_t)o.mx * w.planeb, w.planeb);
+            Store<T>::bstore1(rm, w.gw1, rowb, v.x);
+            Store<T>::bstore1(rm, w.gw2, rowb, v.x);
+        }
+    } else {  // leaves through E
+        const float ve = w.ge_first ? v.x : v.y;
+        Store<T>::bstore1(rout, w.ge1, rowb, ve);
+        if (a.bc[kE] == kReflect) {
+            const rsrc_t rm = make_rsrc(out + (size_t)o.mx * w.planeb, w.planeb);
+            Store<T>::bstore1(rm, w.ge1, rowb, ve);
+            Store<T>::bstore1(rm, w.ge2, rowb, ve);
+        }
+    }
+    const int jg = SY ? a.ny - 1 : 0;  // boundary row the ordinate leaves through
+    if (j == jg) {
+        const uint32_t g1 = (uint32_t)(SY ? a.ny + kGhost : 1) * w.pitchb;  // first ghost row
+        const uint32_t g2 = (uint32_t)(SY ? a.ny + kGhost + 1 : 0) * w.pitchb;
+        Store<T>::bstore2(rout, w.store_off, g1, v);
+        if (w.ragged) Store<T>::bstore1(rout, w.single_off, g1, v.x);
+        if (a.bc[SY ? kN : kS] == kReflect) {
+            const rsrc_t rm = make_rsrc(out + (size_t)o.my * w.planeb, w.planeb);
+            Store<T>::bstore2(rm, w.store_off, g1, v);
+            Store<T>::bstore2(rm, w.store_off, g2, v);
+            if (w.ragged) {
+                Store<T>::bstore1(rm, w.single_off, g1, v.x);
+                Store<T>::bstore1(rm, w.single_off, g2, v.x);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- one ordinate
+// Window row r holds grid row y0 - 2 + r; output row t is window row t + 2.
+template <int ORDER, int MODE, typename T, int TY, int W, bool SX, bool SY>
+__device__ __forceinline__ void stage_ordinate(const StageArgs& a, const OrdConst& o, int k, WaveCtx<TY>& w,
+                                               const float2 (&win)[TY + 4], const float2 (&oldv)[TY],
+                                               double* facc) {
+    constexpr int D = SY ? 0 : 1;  // y-traces of output row t: Ry[t + 1 + D] (south), Ry[t + 2 + D] (north)
+    constexpr float HX = SX ? 0.5f : -0.5f;
+    constexpr float HY = SY ? 0.5f : -0.5f;
+
+    // Reconstructions at the downwind y-face of window rows (eta > 0: top face).
+    float2 Ry[TY + 3];
+    if (ORDER == 2) {
+        float2 dy[TY + 3];  // dy[r] = win[r + 1] - win[r]
+#pragma unroll
+        for (int r = D; r <= TY + 1 + D; ++r) dy[r] = make_float2(win[r + 1].x - win[r].x, win[r + 1].y - win[r].y);
+#pragma unroll
+        for (int r = 1 + D; r <= TY + 1 + D; ++r) {
+            const float mx = minmod(dy[r - 1].x, dy[r].x);
+            const float my = minmod(dy[r - 1].y, dy[r].y);
+            Ry[r] = make_float2(fmaf(HY, mx, win[r].x), fmaf(HY, my, win[r].y));
+        }
+    } else {
+#pragma unroll
+        for (int r = 1 + D; r <= TY + 1 + D; ++r) Ry[r] = win[r];
+    }
+
+    char* const outk = static_cast<char*>(a.psi_out) + (size_t)k * w.planeb;
+    const rsrc_t rout = make_rsrc(outk, w.planeb);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        const int j = w.y0 + t;
+        if (j >= a.ny) break;  // wave-uniform
+        const float c0 = win[t + 2].x, c1 = win[t + 2].y;
+        const float L = lane_from_left(c1);   // cell left of c0
+        const float Rn = lane_from_right(c0);  // cell right of c1
+        float dRx0, dRx1, tW0, tE0, tE1;       // x-differences and traces (west of cell 1 = east of cell 0)
+        if (ORDER == 2) {
+            const float d01 = c1 - c0;
+            const float m0 = minmod(c0 - L, d01), m1 = minmod(d01, Rn - c1);
+            const float R0 = fmaf(HX, m0, c0), R1 = fmaf(HX, m1, c1);
+            if (SX) {
+                const float Rl = lane_from_left(R1);
+                dRx0 = R0 - Rl;
+                dRx1 = R1 - R0;
+                tW0 = Rl;
+                tE0 = R0;
+                tE1 = R1;
+            } else {
+                const float Rr = lane_from_right(R0);
+                dRx0 = R1 - R0;
+                dRx1 = Rr - R1;
+                tW0 = R0;
+                tE0 = R1;
+                tE1 = Rr;
+            }
+        } else {
+            if (SX) {
+                dRx0 = c0 - L;
+                dRx1 = c1 - c0;
+                tW0 = L;
+                tE0 = c0;
+                tE1 = c1;
+            } else {
+                dRx0 = c1 - c0;
+                dRx1 = Rn - c1;
+                tW0 = c0;
+                tE0 = c1;
+                tE1 = Rn;
+            }
+        }
+        const float2 tS = Ry[t + 1 + D], tN = Ry[t + 2 + D];
+
+        if (MODE != kQoiOnly) {
+            float2 v;
+            float d0 = fmaf(-w.st[t].x, c0, w.bb[t].x);
+            float d1 = fmaf(-w.st[t].y, c1, w.bb[t].y);
+            d0 = fmaf(-o.cx, dRx0, d0);
+            d1 = fmaf(-o.cx, dRx1, d1);
+            d0 = fmaf(-o.cy, tN.x - tS.x, d0);
+            d1 = fmaf(-o.cy, tN.y - tS.y, d1);
+            v.x = c0 + d0;
+            v.y = c1 + d1;
+            if (MODE == kAverage) {
+                v.x = 0.5f * (oldv[t].x + v.x);
+                v.y = 0.5f * (oldv[t].y + v.y);
+            }
+            v = Store<T>::round2(v);
+            const uint32_t rowb = (uint32_t)(w.y0 + t + kGhost) * w.pitchb;
+            Store<T>::bstore2(rout, w.store_off, rowb, v);  // halo and partial lanes drop the pair
+            if (w.ragged) Store<T>::bstore1(rout, w.single_off, rowb, v.x);
+            if (w.ghost_wave) write_frame<T, TY, SX, SY>(a, o, k, j, rowb, rout, w, v);
+            w.phacc[t].x = fmaf(o.w, v.x, w.phacc[t].x);
+            w.phacc[t].y = fmaf(o.w, v.y, w.phacc[t].y);
+        }
+
+        if (w.any_tag) {  // wave-uniform: some lane owns a rectangle-boundary face
+            const uint32_t tg = w.tags[t];
+            if (tg & 0xffffu)
+                face_accumulate(tg & 0xffffu, tW0, tE0, tS.x, tN.x, o.fx, o.fy, SX, SY, a.n_rects, facc, kWave * W);
+            if (tg >> 16)
+                face_accumulate(tg >> 16, tE0, tE1, tS.y, tN.y, o.fx, o.fy, SX, SY, a.n_rects, facc, kWave * W);
+        }
+    }
+}
+
+// The ordinate table is read-only for the whole launch: reading it through
+// the constant address space makes it a scalar load, whose wait does not
+// also wait for the next ordinate's window loads.
+using const_ord_ptr = const __attribute__((address_space(4))) OrdConst*;
+
+template <int ORDER, int MODE, typename T, int TY, int W>
+__device__ __forceinline__ void process_ordinate(const StageArgs& a, int k, WaveCtx<TY>& w,
+                                                 const float2 (&win)[TY + 4], const float2 (&oldv)[TY],
+                                                 double* facc) {
+    const const_ord_ptr q = (const_ord_ptr)a.ord + k;
+    OrdConst o;
+    o.cx = q->cx;
+    o.cy = q->cy;
+    o.w = q->w;
+    o.flags = q->flags;
+    o.mx = q->mx;
+    o.my = q->my;
+    o.fx = q->fx;
+    o.fy = q->fy;
+    switch (o.flags & 3) {
+    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, oldv, facc); break;
+    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, oldv, facc); break;
+    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, oldv, facc); break;
+    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, oldv, facc); break;
+    }
+}
+
+// ---------------------------------------------------------------- stage kernel
+template <int ORDER, int MODE, typename T, int TY, int W>
+__global__ void __launch_bounds__(kWave * W) sn_stage_kernel(const StageArgs a) {
+    extern __shared__ double facc_all[];  // [2 n_rects][256] per-thread FP64 face accumulators
+    __shared__ double red[W][kMaxQ];
+    __shared__ float2 rows_lds[2][RowStage<TY, W>::kRows][kWave];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous range of tiles so halo rows and phi stay in its L2.
+    const int nwg = gridDim.x, b = blockIdx.x;
+    const int xcd = b & 7, q8 = b >> 3, per = nwg >> 3, rem = nwg & 7;
+    const int logical = xcd < rem ? xcd * (per + 1) + q8 : rem * (per + 1) + (xcd - rem) * per + q8;
+    const int g = logical % a.G;
+    const int tile = logical / a.G;
+    const int tx = tile % a.ntx;
+    const int tyi = tile / a.ntx;
+
+    WaveCtx<TY> w;
+    w.y0 = (tyi * W + wave) * TY;
+    const int pc = tx * kTileX + 2 * lane;  // padded column of the lane's first cell
+    w.i0 = pc - kGhost;
+    const int pcc = min(pc, a.pitch - 2);   // keep halo lanes of the last tile inside the row
+    w.lane_off = (uint32_t)pcc * (uint32_t)sizeof(T);
+    w.pitchb = (uint32_t)a.pitch * (uint32_t)sizeof(T);
+    w.planeb = (uint32_t)((size_t)a.plane * sizeof(T));
+    const bool out_lane = lane >= 1 && lane <= kWave - 2;
+    w.v0 = out_lane && w.i0 < a.nx;
+    w.v1 = out_lane && w.i0 + 1 < a.nx;
+    w.store_off = w.v1 ? w.lane_off : kDropOffset;
+    w.single_off = (w.v0 && !w.v1) ? w.lane_off : kDropOffset;
+    w.ragged = __any(w.v0 && !w.v1);
+    {
+        const uint32_t es = (uint32_t)sizeof(T);
+        const bool holds_w = w.v0 && w.i0 == 0;
+        const bool holds_e0 = w.v0 && w.i0 == a.nx - 1, holds_e1 = w.v1 && w.i0 + 1 == a.nx - 1;
+        w.gw1 = holds_w ? 1 * es : kDropOffset;
+        w.gw2 = holds_w ? 0 : kDropOffset;
+        w.ge1 = (holds_e0 || holds_e1) ? (uint32_t)(a.nx + kGhost) * es : kDropOffset;
+        w.ge2 = (holds_e0 || holds_e1) ? (uint32_t)(a.nx + kGhost + 1) * es : kDropOffset;
+        w.ge_first = holds_e0;
+        w.ghost_wave = MODE != kQoiOnly && (__any(holds_w || holds_e0 || holds_e1) || w.y0 == 0 ||
+                                            (w.y0 <= a.ny - 1 && a.ny - 1 < w.y0 + TY));
+    }
+    const int ny = a.ny;
+    double* facc = facc_all + tid;
+    for (int s = 0; s < 2 * a.n_rects; ++s) facc[s * kWave * W] = 0.0;
+
+    // Per-cell constants of the stage; mass and absorption of the stage input
+    // (group-0 workgroups only).
+    {
+        double qm = 0.0;
+        double qa[kMaxTallies];
+#pragma unroll
+        for (int t = 0; t < kMaxTallies; ++t) qa[t] = 0.0;
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            const int j = w.y0 + t;
+            w.st[t] = make_float2(0.0f, 0.0f);
+            w.bb[t] = make_float2(0.0f, 0.0f);
+            if (j < ny) {
+                const size_t c = (size_t)(j + kGhost) * a.pitch + pcc;
+                const RegConst r0 = a.reg[a.region[c]], r1 = a.reg[a.region[c + 1]];
+                const float2 ph = *reinterpret_cast<const float2*>(a.phi + c);
+                w.st[t] = make_float2(r0.st, r1.st);
+                w.bb[t] = make_float2(fmaf(r0.cs, ph.x, r0.cq), fmaf(r1.cs, ph.y, r1.cq));
+                if (g == 0) {
+                    const double p0 = w.v0 ? (double)ph.x : 0.0, p1 = w.v1 ? (double)ph.y : 0.0;
+                    qm += p0 + p1;
+#pragma unroll
+                    for (int tt = 0; tt < kMaxTallies; ++tt) {
+                        if (tt == r0.tally) qa[tt] += r0.sa * p0;
+                        if (tt == r1.tally) qa[tt] += r1.sa * p1;
+                    }
+                }
+            }
+        }
+        const double v0 = wave_sum(qm);
+        if (lane == 0) red[wave][0] = v0;
+#pragma unroll
+        for (int tt = 0; tt < kMaxTallies; ++tt) {
+            if (tt < a.n_tallies) {
+                const double v = wave_sum(qa[tt]);
+                if (lane == 0) red[wave][1 + tt] = v;
+            }
+        }
+    }
+
+    uint32_t my_tags = 0;
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        const int j = w.y0 + t;
+        w.tags[t] = face_tags(a, w.i0, j, w.v0) | (face_tags(a, w.i0 + 1, j, w.v1) << 16);
+        my_tags |= w.tags[t];
+        w.phacc[t] = make_float2(0.0f, 0.0f);
+    }
+    w.any_tag = __any(my_tags != 0);
+
+    {
+        const int k0 = g * a.Mg;
+        const int k1 = min(k0 + a.Mg, a.M);
+        const int yw = tyi * W * TY;  // padded row of the workgroup's first staged row
+        // Rows of ordinates k + 1 and k + 2 are in flight in registers (preA /
+        // preB, alternating) while ordinate k is computed from LDS; a row set
+        // is committed to LDS one iteration before it is used, and one barrier
+        // per ordinate separates the two LDS buffers.
+        float2 preA[RowStage<TY, W>::kPer], preB[RowStage<TY, W>::kPer], ocur[TY], onext[TY];
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            ocur[t] = make_float2(0.0f, 0.0f);
+            onext[t] = make_float2(0.0f, 0.0f);
+        }
+        stage_issue<T, TY, W>(a, k0, yw, wave, w, preA);
+        if (k0 + 1 < k1) stage_issue<T, TY, W>(a, k0 + 1, yw, wave, w, preB);
+        stage_commit<TY, W>(rows_lds[0], wave, lane, preA);
+        if (MODE == kAverage) load_old<T, TY>(a, k0, w, ocur);
+        __syncthreads();
+        for (int k = k0; k < k1; k += 2) {
+            // even offset: ordinate k from buffer 0; preB holds k + 1
+            if (k + 2 < k1) stage_issue<T, TY, W>(a, k + 2, yw, wave, w, preA);
+            if (MODE == kAverage && k + 1 < k1) load_old<T, TY>(a, k + 1, w, onext);
+            {
+                float2 win[TY + 4];
+#pragma unroll
+                for (int r = 0; r < TY + 4; ++r) win[r] = rows_lds[0][wave * TY + r][lane];
+                process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, ocur, facc);
+            }
+            if (k + 1 < k1) {
+                stage_commit<TY, W>(rows_lds[1], wave, lane, preB);
+                if (MODE == kAverage) {
+#pragma unroll
+                    for (int t = 0; t < TY; ++t) ocur[t] = onext[t];
+                }
+            }
+            __syncthreads();
+            if (k + 1 >= k1) break;  // workgroup-uniform
+            // odd offset: ordinate k + 1 from buffer 1; preA holds k + 2
+            if (k + 3 < k1) stage_issue<T, TY, W>(a, k + 3, yw, wave, w, preB);
+            if (MODE == kAverage && k + 2 < k1) load_old<T, TY>(a, k + 2, w, onext);
+            {
+                float2 win[TY + 4];
+#pragma unroll
+                for (int r = 0; r < TY + 4; ++r) win[r] = rows_lds[1][wave * TY + r][lane];
+                process_ordinate<ORDER, MODE, T, TY, W>(a, k + 1, w, win, ocur, facc);
+            }
+            if (k + 2 < k1) {
+                stage_commit<TY, W>(rows_lds[0], wave, lane, preA);
+                if (MODE == kAverage) {
+#pragma unroll
+                    for (int t = 0; t < TY; ++t) ocur[t] = onext[t];
+                }
+            }
+            __syncthreads();
+        }
+        if (MODE != kQoiOnly) {
+            char* pphi = reinterpret_cast<char*>(a.phi_part + (size_t)g * (size_t)a.plane);
+#pragma unroll
+            for (int t = 0; t < TY; ++t) {
+                const int j = w.y0 + t;
+                if (j < ny) {
+                    const size_t off = ((size_t)(j + kGhost) * a.pitch + pcc) * sizeof(float);
+                    put_pair<float>(pphi, off, w.phacc[t], w.v0, w.v1);
+                }
+            }
+        }
+    }
+
+    // Workgroup reduction of the QoI partial sums, fixed order.
+    const int nt = a.n_tallies, nr = a.n_rects;
+    for (int s = 0; s < 2 * nr; ++s) {
+        const double v = wave_sum(facc[s * kWave * W]);
+        if (lane == 0) red[wave][1 + nt + s] = v;
+    }
+    __syncthreads();
+    if (tid < a.nq) {
+        double tot = red[0][tid];
+#pragma unroll
+        for (int ww = 1; ww < W; ++ww) tot += red[ww][tid];
+        a.qpart[(size_t)tid * a.n_wg + b] = tot;
+    }
+}
+
+template <int ORDER, int MODE, typename T, int TY>
+static void launch_w(int waves, const StageArgs& a, hipStream_t s) {
+    const size_t lds_per_thread = (size_t)2 * a.n_rects * sizeof(double);
+    switch (waves) {
+    case 4: hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 4>), dim3(a.n_wg), dim3(kWave * 4), lds_per_thread * kWave * 4, s, a); break;
+    case 8: hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 8>), dim3(a.n_wg), dim3(kWave * 8), lds_per_thread * kWave * 8, s, a); break;
+    default: hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 16>), dim3(a.n_wg), dim3(kWave * 16), lds_per_thread * kWave * 16, s, a); break;
+    }
+}
+
+template <int ORDER, typename T>
+static hipError_t launch_stage_tu(int mode, int rows, int waves, const StageArgs& a, hipStream_t s) {
+    if (waves != 4 && waves != 8 && waves != 16) return hipErrorInvalidValue;
+    if (rows == 2) {
+        if (mode == kUpdate) launch_w<ORDER, kUpdate, T, 2>(waves, a, s);
+        else if (mode == kAverage) launch_w<ORDER, kAverage, T, 2>(waves, a, s);
+        else launch_w<ORDER, kQoiOnly, T, 2>(waves, a, s);
+    } else if (rows == 4) {
+        if (mode == kUpdate) launch_w<ORDER, kUpdate, T, 4>(waves, a, s);
+        else if (mode == kAverage) launch_w<ORDER, kAverage, T, 4>(waves, a, s);
+        else launch_w<ORDER, kQoiOnly, T, 4>(waves, a, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace snk

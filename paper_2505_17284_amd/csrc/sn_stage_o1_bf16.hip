@@ -1,0 +1,10 @@
+// Stage kernels for order 1, psi stored as bf16 (instantiations of sn_stage_impl.h).
+#include "sn_stage_impl.h"
+
+namespace snk {
+
+hipError_t launch_stage_o1_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s) {
+    return launch_stage_tu<1, uint16_t>(mode, rows, waves, a, s);
+}
+
+}  // namespace snk

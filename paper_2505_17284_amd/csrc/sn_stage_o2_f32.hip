@@ -1,0 +1,10 @@
+// Stage kernels for order 2, psi stored as f32 (instantiations of sn_stage_impl.h).
+#include "sn_stage_impl.h"
+
+namespace snk {
+
+hipError_t launch_stage_o2_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s) {
+    return launch_stage_tu<2, float>(mode, rows, waves, a, s);
+}
+
+}  // namespace snk

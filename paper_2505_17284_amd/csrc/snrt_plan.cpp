@@ -66,12 +66,12 @@ struct sn_plan {
     // derived
     int nt = 0;
     double dt = 0;
-    int pitch = 0;
-    int64_t plane = 0;
-    int G = 1, Mg = 1, rows = 8;
+    int pitch = 0, ny_alloc = 0;
+    int64_t plane = 0, origin = 0;
+    int G = 1, Mg = 1, rows = 2, waves = 8;
     int ntx = 0, nty = 0, n_wg = 0, nq = 0;
     size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
-    size_t off_phi[2] = {0, 0}, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
+    size_t off_phi = 0, off_phi_part = 0, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
            off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
     double source = 0;  // (sum w) h^2 sum_cells Q
     std::vector<OrdConst> ord_h;
@@ -84,8 +84,7 @@ struct sn_plan {
     char* scratch = nullptr;
     bool bound = false, inited = false;
     int64_t step = 0;
-    int cur = 0;      // buffer holding the current state
-    int phi_cur = 0;  // phi buffer holding phi of the current state
+    int cur = 0;  // buffer holding the current state
 
     // timing
     bool timing = false;
@@ -221,39 +220,51 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     return SN_OK;
 }
 
-void default_shape(const sn_plan* P, int* group_size, int* rows) {
-    // Rows per wave: 8 keeps the y-halo at 3/8 of a tile row block while the
-    // per-cell registers stay small. Ordinate groups: enough workgroups to fill
-    // 256 CUs several times over, without making the phi partials (one FP32 per
-    // cell per group, read and written each stage) a visible share of traffic.
-    *rows = P->ny >= 64 ? 8 : 4;
-    const int wg_rows = kWavesPerWG * *rows;
-    const long tiles = (long)((P->nx + kXOut - 1) / kXOut) * ((P->ny + wg_rows - 1) / wg_rows);
+void default_shape(const sn_plan* P, int* group_size, int* rows, int* waves) {
+    // Two rows per wave keep the staged windows, the per-cell constants and the
+    // reconstructions within ~80 VGPRs. Eight waves stacked per workgroup stage
+    // 4 halo rows per 16 output rows (1.25x the rows read). Ordinate groups:
+    // split until the launch holds ~4 K workgroups (16 per CU), keeping at
+    // least 8 ordinates per group so the per-workgroup set-up and the group's
+    // phi partial stay small.
+    *rows = 2;
+    *waves = P->ny >= 64 ? 8 : 4;
+    const int wg_rows = *waves * *rows;
+    const long tiles = (long)((P->nx + kTileX - 1) / kTileX) * ((P->ny + wg_rows - 1) / wg_rows);
     int g = 1;
-    while (g < 16 && tiles * g < 2048 && P->M / (g * 2) >= 4) g *= 2;
+    while (tiles * g < 4096 && (P->M + 2 * g - 1) / (2 * g) >= 8) g *= 2;
     *group_size = (P->M + g - 1) / g;
 }
 
-sn_status derive(sn_plan* P, int group_size, int rows) {
+sn_status derive(sn_plan* P, int group_size, int rows, int waves) {
     // dt = CFL * h (Sec. 5.1.3), adjusted so that N_t dt = T (Sec. 4.3).
     const double r = P->t_end / (P->cfl * P->h);
     P->nt = std::max(1, (int)std::ceil(r - 1e-9));
     P->dt = P->t_end / P->nt;
 
-    int gs = 0, rw = 0;
-    default_shape(P, &gs, &rw);
+    int gs = 0, rw = 0, wv = 0;
+    default_shape(P, &gs, &rw, &wv);
     if (group_size > 0) gs = std::min(group_size, P->M);
     if (rows > 0) rw = rows;
-    if (!supported_rows_per_wave(rw)) return fail(SN_ERR_UNSUPPORTED, "rows_per_wave %d not compiled", rw);
+    if (waves > 0) wv = waves;
+    if (!supported_shape(rw, wv))
+        return fail(SN_ERR_UNSUPPORTED, "launch shape rows_per_wave %d, waves %d not compiled", rw, wv);
     P->Mg = gs;
     P->G = (P->M + gs - 1) / gs;
     P->rows = rw;
+    P->waves = wv;
     P->elem = P->dtype == SN_F32 ? 4 : 2;
+    // Rows of 64-byte multiples holding the interior plus the two-cell ghost
+    // frame; enough rows that every window of the last row of tiles is inside.
     const int align_elems = (int)(64 / P->elem);
-    P->pitch = (P->nx + align_elems - 1) / align_elems * align_elems;
-    P->plane = (int64_t)P->ny * P->pitch;
-    P->ntx = (P->nx + kXOut - 1) / kXOut;
-    P->nty = (P->ny + kWavesPerWG * rw - 1) / (kWavesPerWG * rw);
+    P->pitch = (P->nx + 2 * kGhost + align_elems - 1) / align_elems * align_elems;
+    P->ntx = (P->nx + kTileX - 1) / kTileX;
+    P->nty = (P->ny + wv * rw - 1) / (wv * rw);
+    P->ny_alloc = P->nty * wv * rw + 2 * kGhost;
+    P->plane = (int64_t)P->ny_alloc * P->pitch;
+    P->origin = (int64_t)kGhost * P->pitch + kGhost;
+    if ((uint64_t)P->plane * P->elem >= (1ull << 31))
+        return fail(SN_ERR_UNSUPPORTED, "one psi plane exceeds 2 GiB (grid %d x %d)", P->nx, P->ny);
     const int64_t n_wg = (int64_t)P->ntx * P->nty * P->G;
     if (n_wg > (int64_t)0x7fffffff) return fail(SN_ERR_UNSUPPORTED, "too many workgroups");
     P->n_wg = (int)n_wg;
@@ -261,11 +272,10 @@ sn_status derive(sn_plan* P, int group_size, int rows) {
 
     P->psi_bytes = align256((size_t)P->M * (size_t)P->plane * P->elem);
     size_t off = 0;
-    const size_t phi_bytes = align256((size_t)P->G * (size_t)P->plane * sizeof(float));
-    P->off_phi[0] = off;
-    off += phi_bytes;
-    P->off_phi[1] = off;
-    off += phi_bytes;
+    P->off_phi = off;
+    off += align256((size_t)P->plane * sizeof(float));
+    P->off_phi_part = off;
+    off += align256((size_t)P->G * (size_t)P->plane * sizeof(float));
     P->off_ord = off;
     off += align256((size_t)P->M * sizeof(OrdConst));
     P->off_reg = off;
@@ -310,7 +320,7 @@ sn_status derive(sn_plan* P, int group_size, int rows) {
     }
     P->region_h.assign((size_t)P->plane, 0);
     for (int j = 0; j < P->ny; ++j)
-        std::memcpy(&P->region_h[(size_t)j * P->pitch], &P->region[(size_t)j * P->nx], P->nx);
+        std::memcpy(&P->region_h[(size_t)(P->origin + (int64_t)j * P->pitch)], &P->region[(size_t)j * P->nx], P->nx);
     const double h2 = P->h * P->h;
     P->scale_h.assign(kMaxQ, 0.0);
     P->scale_h[0] = h2;
@@ -324,14 +334,13 @@ sn_status derive(sn_plan* P, int group_size, int rows) {
     return SN_OK;
 }
 
-StageArgs stage_args(const sn_plan* P, int mode, const char* in, const char* old, char* out, int phi_in,
-                     int phi_out) {
+StageArgs stage_args(const sn_plan* P, int mode, const char* in, const char* old, char* out) {
     StageArgs a{};
     a.psi_in = in;
     a.psi_old = old;
     a.psi_out = out;
-    a.phi_in = P->sp<float>(P->off_phi[phi_in]);
-    a.phi_out = P->sp<float>(P->off_phi[phi_out]);
+    a.phi = P->sp<float>(P->off_phi);
+    a.phi_part = P->sp<float>(P->off_phi_part);
     a.ord = P->sp<OrdConst>(P->off_ord);
     a.reg = P->sp<RegConst>(P->off_reg);
     a.region = P->sp<uint8_t>(P->off_region);
@@ -349,14 +358,27 @@ StageArgs stage_args(const sn_plan* P, int mode, const char* in, const char* old
     a.n_tallies = P->n_tallies;
     a.n_rects = P->n_rects;
     a.nq = P->nq;
-    for (int s = 0; s < 4; ++s) {
-        a.bc[s] = P->bc[s];
-        a.ghost[s] = P->bc[s] == SN_BC_INFLOW ? (float)P->inflow[s] : 0.0f;
-    }
+    for (int s = 0; s < 4; ++s) a.bc[s] = P->bc[s];
     for (int r = 0; r < P->n_rects; ++r)
         for (int e = 0; e < 4; ++e) a.rect[r][e] = P->rects[r][e];
     (void)mode;
     return a;
+}
+
+GhostArgs ghost_args(const sn_plan* P, char* psi) {
+    GhostArgs ga{};
+    ga.psi = psi;
+    ga.ord = P->sp<OrdConst>(P->off_ord);
+    ga.plane = P->plane;
+    ga.nx = P->nx;
+    ga.ny = P->ny;
+    ga.pitch = P->pitch;
+    ga.M = P->M;
+    for (int side = 0; side < 4; ++side) {
+        ga.bc[side] = P->bc[side];
+        ga.ghost[side] = P->bc[side] == SN_BC_INFLOW ? (float)P->inflow[side] : 0.0f;
+    }
+    return ga;
 }
 
 sn_status flush_events(sn_plan* P) {
@@ -384,7 +406,7 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
         out = P->psi[0];
     }
     if (kind < 0) out = nullptr;
-    StageArgs a = stage_args(P, mode, in, old, out, P->phi_cur, P->phi_cur ^ 1);
+    StageArgs a = stage_args(P, mode, in, old, out);
     const bool timed = P->timing && allow_timing && kind >= 0;
     if (timed) {
         if (P->ev_used == (int)P->ev_start.size()) {
@@ -393,13 +415,21 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
         }
         HIP_TRY(hipEventRecord(P->ev_start[P->ev_used], s), "hipEventRecord");
     }
-    HIP_TRY(launch_stage(P->order, mode, P->dtype, P->rows, a, s), "stage launch");
+    HIP_TRY(launch_stage(P->order, mode, P->dtype, P->rows, P->waves, a, s), "stage launch");
     if (timed) {
         HIP_TRY(hipEventRecord(P->ev_stop[P->ev_used], s), "hipEventRecord");
         P->ev_kind[P->ev_used] = kind;
         P->ev_used++;
     }
     FinalizeArgs f{};
+    f.phi_part = P->sp<float>(P->off_phi_part);
+    f.phi = P->sp<float>(P->off_phi);
+    f.plane = P->plane;
+    f.nx = P->nx;
+    f.ny = P->ny;
+    f.pitch = P->pitch;
+    f.G = P->G;
+    f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->nx * P->ny + 255) / 256);
     f.qpart = P->sp<double>(P->off_qpart);
     f.scale = P->sp<double>(P->off_scale);
     f.inst = P->sp<double>(P->off_inst);
@@ -419,14 +449,11 @@ sn_status launch_steps(sn_plan* P, int n, hipStream_t s, bool allow_timing) {
             st = launch_stage_pair(P, 0, s, allow_timing);
             if (st != SN_OK) return st;
             P->cur ^= 1;
-            P->phi_cur ^= 1;
         } else {
             st = launch_stage_pair(P, 1, s, allow_timing);
             if (st != SN_OK) return st;
-            P->phi_cur ^= 1;
             st = launch_stage_pair(P, 2, s, allow_timing);
             if (st != SN_OK) return st;
-            P->phi_cur ^= 1;
         }
         P->step++;
     }
@@ -446,8 +473,8 @@ sn_status run_steps(sn_plan* P, int n, hipStream_t s) {
     int done = 0;
     if (P->graph_steps > 0 && !P->timing) {
         const int K = P->graph_steps;
-        // the graph covers K steps and starts from buffer/phi parity 0
-        if (n >= K && P->cur == 0 && P->phi_cur == 0) {
+        // the graph covers K steps and starts from buffer parity 0
+        if (n >= K && P->cur == 0) {
             if (!P->graph_exec) {
                 hipStream_t cs;
                 HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
@@ -497,16 +524,17 @@ const char* sn_status_str(sn_status s) {
 }
 
 sn_status sn_plan_create_tuned(const sn_problem* problem, int32_t group_size, int32_t rows_per_wave,
-                               sn_plan** out) {
+                               int32_t waves_per_group, sn_plan** out) {
     if (!out) return fail(SN_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (group_size < 0 || rows_per_wave < 0) return fail(SN_ERR_INVALID, "negative launch shape");
+    if (group_size < 0 || rows_per_wave < 0 || waves_per_group < 0)
+        return fail(SN_ERR_INVALID, "negative launch shape");
     sn_plan* P = new (std::nothrow) sn_plan();
     if (!P) return fail(SN_ERR_OOM, "plan allocation failed");
     sn_status st;
     try {
         st = validate_and_copy(problem, P);
-        if (st == SN_OK) st = derive(P, group_size, rows_per_wave);
+        if (st == SN_OK) st = derive(P, group_size, rows_per_wave, waves_per_group);
     } catch (const std::bad_alloc&) {
         st = fail(SN_ERR_OOM, "host allocation failed");
     }
@@ -519,7 +547,7 @@ sn_status sn_plan_create_tuned(const sn_problem* problem, int32_t group_size, in
 }
 
 sn_status sn_plan_create(const sn_problem* problem, sn_plan** out) {
-    return sn_plan_create_tuned(problem, 0, 0, out);
+    return sn_plan_create_tuned(problem, 0, 0, 0, out);
 }
 
 sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
@@ -533,6 +561,7 @@ sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
     out->n_groups = P->G;
     out->group_size = P->Mg;
     out->rows_per_wave = P->rows;
+    out->waves_per_group = P->waves;
     out->n_workgroups = P->n_wg;
     out->psi_bytes = P->psi_bytes;
     out->scratch_bytes = P->scratch_bytes;
@@ -573,23 +602,23 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_integ), 0, kMaxQ * sizeof(double), s), "clear integrals");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_inst), 0, kMaxQ * sizeof(double), s), "clear QoIs");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_flags), 0, sizeof(int32_t), s), "clear flags");
-    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_phi[0]), 0, P->off_phi[1] - P->off_phi[0], s), "clear phi");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_phi), 0, P->plane * sizeof(float), s), "clear phi");
     HIP_TRY(hipMemsetAsync(P->psi[0], 0, P->psi_bytes, s), "clear psi A");
     HIP_TRY(hipMemsetAsync(P->psi[1], 0, P->psi_bytes, s), "clear psi B");
     P->cur = 0;
-    P->phi_cur = 0;
     P->step = 0;
     drop_graph(P);
     if (psi0) {
-        const size_t rows = (size_t)P->M * P->ny;
         if (P->dtype == SN_F32) {
-            HIP_TRY(hipMemcpy2DAsync(P->psi[0], P->pitch * sizeof(float), psi0, P->nx * sizeof(float),
-                                     P->nx * sizeof(float), rows, hipMemcpyHostToDevice, s), "upload psi0");
+            for (int k = 0; k < P->M; ++k)
+                HIP_TRY(hipMemcpy2DAsync(P->psi[0] + (k * P->plane + P->origin) * sizeof(float), P->pitch * sizeof(float),
+                                         psi0 + (size_t)k * P->ny * P->nx, P->nx * sizeof(float), P->nx * sizeof(float),
+                                         P->ny, hipMemcpyHostToDevice, s), "upload psi0");
             HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         } else {
             std::vector<uint16_t> tmp;
             try {
-                tmp.resize(rows * P->nx);
+                tmp.resize((size_t)P->M * P->ny * P->nx);
             } catch (const std::bad_alloc&) {
                 return fail(SN_ERR_OOM, "host staging for psi0");
             }
@@ -602,23 +631,26 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
                     u = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
                 tmp[e] = (uint16_t)u;
             }
-            HIP_TRY(hipMemcpy2DAsync(P->psi[0], P->pitch * 2, tmp.data(), P->nx * 2, P->nx * 2, rows,
-                                     hipMemcpyHostToDevice, s), "upload psi0");
+            for (int k = 0; k < P->M; ++k)
+                HIP_TRY(hipMemcpy2DAsync(P->psi[0] + (k * P->plane + P->origin) * 2, P->pitch * 2,
+                                         tmp.data() + (size_t)k * P->ny * P->nx, P->nx * 2, P->nx * 2, P->ny,
+                                         hipMemcpyHostToDevice, s), "upload psi0");
             HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         }
         PhiInitArgs pa{};
         pa.psi = P->psi[0];
-        pa.phi = P->sp<float>(P->off_phi[0]);
+        pa.phi = P->sp<float>(P->off_phi);
         pa.ord = P->sp<OrdConst>(P->off_ord);
         pa.plane = P->plane;
         pa.nx = P->nx;
         pa.ny = P->ny;
         pa.pitch = P->pitch;
         pa.M = P->M;
-        pa.G = P->G;
-        pa.Mg = P->Mg;
         HIP_TRY(launch_phi_init(P->dtype, pa, s), "phi init launch");
     }
+    // Ghost frames of both buffers: B's incoming vacuum/inflow ghosts are
+    // constants the stages never rewrite.
+    for (int b = 0; b < 2; ++b) HIP_TRY(launch_ghost_fill(P->dtype, ghost_args(P, P->psi[b]), s), "ghost fill launch");
     // QoIs of the initial state: keep mass(0) for the balance residual.
     P->inited = true;
     sn_status st = launch_stage_pair(P, -1, s, false);
@@ -699,15 +731,19 @@ sn_status sn_plan_read_psi(const sn_plan* P, float* host_out, void* stream) {
     if (!P || !host_out) return fail(SN_ERR_INVALID, "NULL argument");
     if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
     hipStream_t s = (hipStream_t)stream;
-    const size_t rows = (size_t)P->M * P->ny;
     if (P->dtype == SN_F32) {
-        HIP_TRY(hipMemcpy2DAsync(host_out, P->nx * sizeof(float), P->psi[P->cur], P->pitch * sizeof(float),
-                                 P->nx * sizeof(float), rows, hipMemcpyDeviceToHost, s), "read psi");
+        for (int k = 0; k < P->M; ++k)
+            HIP_TRY(hipMemcpy2DAsync(host_out + (size_t)k * P->ny * P->nx, P->nx * sizeof(float),
+                                     P->psi[P->cur] + (k * P->plane + P->origin) * sizeof(float),
+                                     P->pitch * sizeof(float), P->nx * sizeof(float), P->ny, hipMemcpyDeviceToHost, s),
+                    "read psi");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     } else {
-        std::vector<uint16_t> tmp(rows * P->nx);
-        HIP_TRY(hipMemcpy2DAsync(tmp.data(), P->nx * 2, P->psi[P->cur], P->pitch * 2, P->nx * 2, rows,
-                                 hipMemcpyDeviceToHost, s), "read psi");
+        std::vector<uint16_t> tmp((size_t)P->M * P->ny * P->nx);
+        for (int k = 0; k < P->M; ++k)
+            HIP_TRY(hipMemcpy2DAsync(tmp.data() + (size_t)k * P->ny * P->nx, P->nx * 2,
+                                     P->psi[P->cur] + (k * P->plane + P->origin) * 2, P->pitch * 2, P->nx * 2, P->ny,
+                                     hipMemcpyDeviceToHost, s), "read psi");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         for (size_t e = 0; e < tmp.size(); ++e) {
             uint32_t u = (uint32_t)tmp[e] << 16;
@@ -721,16 +757,10 @@ sn_status sn_plan_read_phi(const sn_plan* P, float* host_out, void* stream) {
     if (!P || !host_out) return fail(SN_ERR_INVALID, "NULL argument");
     if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<float> tmp((size_t)P->G * P->plane);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), P->sp<char>(P->off_phi[P->phi_cur]), tmp.size() * sizeof(float),
-                           hipMemcpyDeviceToHost, s), "read phi");
+    HIP_TRY(hipMemcpy2DAsync(host_out, P->nx * sizeof(float), P->sp<char>(P->off_phi) + P->origin * sizeof(float),
+                             P->pitch * sizeof(float),
+                             P->nx * sizeof(float), P->ny, hipMemcpyDeviceToHost, s), "read phi");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-    for (int j = 0; j < P->ny; ++j)
-        for (int i = 0; i < P->nx; ++i) {
-            float acc = 0.0f;
-            for (int g = 0; g < P->G; ++g) acc += tmp[(size_t)g * P->plane + (size_t)j * P->pitch + i];
-            host_out[(size_t)j * P->nx + i] = acc;
-        }
     return SN_OK;
 }
 

@@ -25,11 +25,11 @@ def _torch():
     return torch
 
 
-def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0) -> dict:
+def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0) -> dict:
     """Derived constants and buffer sizes of a plan (host only, no GPU)."""
     m = MarshalledProblem(problem)
     h = ctypes.c_void_p()
-    check(lib().sn_plan_create_tuned(ctypes.byref(m.struct), group_size, rows_per_wave,
+    check(lib().sn_plan_create_tuned(ctypes.byref(m.struct), group_size, rows_per_wave, waves_per_group,
                                      ctypes.byref(h)), "sn_plan_create")
     try:
         info = SnPlanInfo()
@@ -58,8 +58,8 @@ def qoi_dicts(problem, q: SnQoi):
 class Plan:
     """A bound, initialised solve on one GPU."""
 
-    def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, device: str = "cuda:0",
-                 psi0=None, graph_steps: int = 0):
+    def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
+                 device: str = "cuda:0", psi0=None, graph_steps: int = 0):
         torch = _torch()
         assert problem.n_tallies <= MAX_TALLIES and problem.n_rects <= MAX_RECTS
         self.problem = problem
@@ -67,7 +67,7 @@ class Plan:
         self._m = MarshalledProblem(problem)
         self.h = ctypes.c_void_p()
         check(lib().sn_plan_create_tuned(ctypes.byref(self._m.struct), group_size, rows_per_wave,
-                                         ctypes.byref(self.h)), "sn_plan_create")
+                                         waves_per_group, ctypes.byref(self.h)), "sn_plan_create")
         info = SnPlanInfo()
         check(lib().sn_plan_get_info(self.h, ctypes.byref(info)), "sn_plan_get_info")
         self.info = {f: getattr(info, f) for f, _ in SnPlanInfo._fields_}

@@ -11,7 +11,14 @@ Tolerances (derivation in the design notes):
   * fields after n stages: |gpu - oracle| <= FIELD_RTOL |oracle| + atol with
     atol = FIELD_ATOL(n) * max|oracle|: FP32 rounding of each stage's update
     is a few ulps of the largest value in the stencil and accumulates at most
-    linearly with the number of stages.
+    linearly with the number of stages. For short runs every element must
+    meet it.
+  * long runs (more than SHORT_STAGES stages): the minmod scheme amplifies
+    persistent FP32 rounding at isolated limiter-switching points (a float32
+    NumPy model of the scheme shows it, tests/test_fp32_model.py), so there
+    the field must meet: relative L1 error <= LONG_L1, at most LONG_FRAC of
+    the elements outside the per-element bound above, and every element
+    within LONG_CAP of the peak.
 """
 
 import numpy as np
@@ -19,6 +26,10 @@ import numpy as np
 QOI_RTOL = 1e-5
 QOI_FLOOR = 1e-6
 FIELD_RTOL = 1e-5
+SHORT_STAGES = 16
+LONG_L1 = 1e-6
+LONG_FRAC = 1e-3
+LONG_CAP = 1e-3
 
 
 def field_atol(stages: int) -> float:
@@ -60,7 +71,8 @@ def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rt
     return ok, "\n".join(lines)
 
 
-def compare_field(gpu: np.ndarray, orc: np.ndarray, stages: int, rtol: float = FIELD_RTOL, atol_scale=None):
+def compare_field(gpu: np.ndarray, orc: np.ndarray, stages: int, rtol: float = FIELD_RTOL, atol_scale=None,
+                  strict=None):
     gpu = np.asarray(gpu, dtype=np.float64)
     orc = np.asarray(orc, dtype=np.float64)
     assert gpu.shape == orc.shape, (gpu.shape, orc.shape)
@@ -69,7 +81,13 @@ def compare_field(gpu: np.ndarray, orc: np.ndarray, stages: int, rtol: float = F
     err = np.abs(gpu - orc)
     bad = err > rtol * np.abs(orc) + atol
     worst = np.unravel_index(int(np.argmax(err - rtol * np.abs(orc))), err.shape)
-    rep = (f"max|err|={err.max():.3e} (peak {peak:.3e}, atol {atol:.2e}), "
+    l1 = float(err.sum() / max(np.abs(orc).sum(), 1e-300))
+    frac = float(bad.mean())
+    rep = (f"max|err|={err.max():.3e} (peak {peak:.3e}, atol {atol:.2e}), L1 {l1:.2e}, "
            f"bad={int(bad.sum())}/{bad.size}, worst at {tuple(int(x) for x in worst)}: "
            f"gpu={gpu[worst]:.9g} orc={orc[worst]:.9g}")
-    return not bad.any(), rep
+    strict = stages <= SHORT_STAGES if strict is None else strict
+    if strict:
+        return not bad.any(), rep
+    ok = l1 <= LONG_L1 and frac <= LONG_FRAC and err.max() <= LONG_CAP * peak
+    return ok, rep + " [long-run rule]"

@@ -98,15 +98,17 @@ def test_degenerate_and_tile_edge_shapes(sv, orc, shape, order):
     _check(p, g_, o_, 3)
 
 
-@pytest.mark.parametrize("rows", [4, 8, 16])
+@pytest.mark.parametrize("rows", [2, 4])
+@pytest.mark.parametrize("waves", [4, 8, 16])
 @pytest.mark.parametrize("group", [1, 5, 32])
-def test_launch_shapes_agree(sv, orc, rows, group):
-    """Every compiled rows-per-wave and several ordinate-group sizes (ragged
-    last group) give the oracle's answer."""
+def test_launch_shapes_agree(sv, orc, rows, waves, group):
+    """Every compiled launch shape (rows per wave, waves per workgroup) and
+    several ordinate-group sizes (ragged last group) give the oracle's answer."""
     p = I.random_materials(73, 70, 4, seed=5, order=2, stepper=I.HEUN, bc=BCS["mixed"][0],
                            inflow=BCS["mixed"][1], M=32, h=0.05)
     psi0 = I.random_state(p, 9, "smooth")
-    g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0, group_size=group, rows_per_wave=rows)
+    g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0, group_size=group, rows_per_wave=rows,
+                       waves_per_group=waves)
     _check(p, g_, o_, 2)
 
 
