@@ -23,6 +23,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest():
+    """SHA-256 over the kernel and ABI sources: ties a profile summary to the code it measured."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2505_17284_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp")))
+    files.append(os.path.join(ROOT, "include", "snrt.h"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(dtype):
+    """HBM bytes per launch of the Heun stage-2 kernel from the committed rocprofv3
+    counter summary, or None when the summary is missing or was taken on other sources."""
+    path = os.path.join(PROFILES, f"stage_heun2_lattice700_M256_{dtype}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != source_digest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def algorithmic_bytes(problem, plan_info, kind):
@@ -69,6 +102,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
@@ -87,7 +121,8 @@ def main():
     problem = I.config(2).replace(psi_dtype=args.dtype)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    plan = solver.Plan(problem, group_size=args.group, rows_per_wave=args.rows, device="cuda:0")
+    plan = solver.Plan(problem, group_size=args.group, rows_per_wave=args.rows, waves_per_group=args.waves,
+                       device="cuda:0")
     info = plan.info
     print(f"[bench] plan: {info}", file=sys.stderr, flush=True)
     plan.run(args.warmup, unbounded=True)
@@ -111,6 +146,10 @@ def main():
     stage1_ms = ms[1] / max(counts[1], 1)
     stage1_gbs = algorithmic_bytes(problem, info, 1) / (stage1_ms * 1e-3) / 1e9
     step_bytes = algorithmic_bytes(problem, info, 1) + algorithmic_bytes(problem, info, 2)
+    traffic = None
+    default_shape = not (args.group or args.rows or args.waves)
+    if default_shape:
+        traffic = measured_traffic(args.dtype)
     line = {
         "metric": "cell-ordinate updates/s",
         "value": ups,
@@ -127,11 +166,15 @@ def main():
         "config": {"workload": "lattice700_M256_heun2", "nx": problem.nx, "ny": problem.ny,
                    "ordinates": problem.M, "order": problem.order, "stepper": "heun",
                    "cfl": problem.cfl, "psi_storage": args.dtype,
-                   "group_size": info["group_size"], "rows_per_wave": info["rows_per_wave"]},
+                   "group_size": info["group_size"], "rows_per_wave": info["rows_per_wave"],
+                   "waves_per_group": info["waves_per_group"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sn_stage_kernel<2, kAverage> (Heun stage 2)",
-                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_launch},
+                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_launch,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
+                                     "calibrated on a device copy)",
+                     "traffic_over_algorithmic": None if traffic is None else traffic / bytes_launch},
         "stage1": {"kernel_avg_ms": stage1_ms, "achieved_GBs": stage1_gbs},
         "step_algorithmic_GBs": step_bytes / (secs / args.steps) / 1e9,
         "roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / (step_bytes / problem.cell_ordinates),

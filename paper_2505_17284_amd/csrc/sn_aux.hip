@@ -86,25 +86,48 @@ __global__ void __launch_bounds__(256) sn_ghost_fill_kernel(const GhostArgs a) {
 // Workgroups [0, nq): one per QoI slot; sums the per-workgroup partials in a
 // fixed order (deterministic), scales, and accumulates the time integral.
 // Workgroups [nq, nq + n_phi_wg): phi = sum over groups of the stage's
-// partial scalar fluxes, in group order, for every interior cell.
+// partial scalar fluxes, in group order, for every interior cell (4 padded
+// columns per thread, ny * pitch / 4 threads).
 __global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs a) {
     if ((int)blockIdx.x >= a.nq) {
-        const int64_t c = (int64_t)(blockIdx.x - a.nq) * 256 + threadIdx.x;
-        if (c >= (int64_t)a.nx * a.ny) return;
-        const int64_t j = c / a.nx, i = c - j * a.nx;
-        const int64_t off = (j + kGhost) * a.pitch + i + kGhost;
-        // all loads first (independent), then the sum in group order
-        float part[32];
+        // four consecutive padded columns per thread (16-byte aligned: the
+        // pitch is a multiple of 16 elements); only interior cells are written
+        const int per_row = a.pitch / 4;
+        const int64_t u = (int64_t)(blockIdx.x - a.nq) * 256 + threadIdx.x;
+        if (u >= (int64_t)a.ny * per_row) return;
+        const int j = (int)(u / per_row), c4 = (int)(u - (int64_t)j * per_row);
+        const int64_t off = (int64_t)(j + kGhost) * a.pitch + 4 * c4;
+        float4 part[16];
         const int G = a.G;
 #pragma unroll
-        for (int g = 0; g < 32; ++g)
-            if (g < G) part[g] = a.phi_part[(int64_t)g * a.plane + off];
-        float acc = part[0];
+        for (int g = 0; g < 16; ++g)
+            if (g < G) part[g] = *reinterpret_cast<const float4*>(a.phi_part + (int64_t)g * a.plane + off);
+        float4 acc = part[0];
 #pragma unroll
-        for (int g = 1; g < 32; ++g)
-            if (g < G) acc += part[g];
-        for (int g = 32; g < G; ++g) acc += a.phi_part[(int64_t)g * a.plane + off];
-        a.phi[off] = acc;
+        for (int g = 1; g < 16; ++g) {
+            if (g < G) {
+                acc.x += part[g].x;
+                acc.y += part[g].y;
+                acc.z += part[g].z;
+                acc.w += part[g].w;
+            }
+        }
+        for (int g = 16; g < G; ++g) {
+            const float4 p = *reinterpret_cast<const float4*>(a.phi_part + (int64_t)g * a.plane + off);
+            acc.x += p.x;
+            acc.y += p.y;
+            acc.z += p.z;
+            acc.w += p.w;
+        }
+        const int i0 = 4 * c4 - kGhost;  // interior column of the first of the four
+        if (i0 >= 0 && i0 + 3 < a.nx) {
+            *reinterpret_cast<float4*>(a.phi + off) = acc;
+        } else {
+            const float v[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i0 + e >= 0 && i0 + e < a.nx) a.phi[off + e] = v[e];
+        }
         return;
     }
     const int s = blockIdx.x;

@@ -222,13 +222,14 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
 
 void default_shape(const sn_plan* P, int* group_size, int* rows, int* waves) {
     // Two rows per wave keep the staged windows, the per-cell constants and the
-    // reconstructions within ~80 VGPRs. Eight waves stacked per workgroup stage
-    // 4 halo rows per 16 output rows (1.25x the rows read). Ordinate groups:
+    // reconstructions within ~80 VGPRs. Four waves per workgroup: taller
+    // workgroups stage fewer halo rows but measured slower on the 700 x 700
+    // lattice, the halo rows mostly hitting L2 anyway. Ordinate groups:
     // split until the launch holds ~4 K workgroups (16 per CU), keeping at
     // least 8 ordinates per group so the per-workgroup set-up and the group's
     // phi partial stay small.
     *rows = 2;
-    *waves = P->ny >= 64 ? 8 : 4;
+    *waves = 4;
     const int wg_rows = *waves * *rows;
     const long tiles = (long)((P->nx + kTileX - 1) / kTileX) * ((P->ny + wg_rows - 1) / wg_rows);
     int g = 1;
@@ -429,7 +430,7 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
     f.ny = P->ny;
     f.pitch = P->pitch;
     f.G = P->G;
-    f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->nx * P->ny + 255) / 256);
+    f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
     f.qpart = P->sp<double>(P->off_qpart);
     f.scale = P->sp<double>(P->off_scale);
     f.inst = P->sp<double>(P->off_inst);
