@@ -208,6 +208,75 @@ sn_status sn_plan_kernel_ms(sn_plan *plan, double ms[4], int64_t counts[4]);
 
 void sn_plan_destroy(sn_plan *plan);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent solves advanced together (the batched uncertainty-
+ * quantification and serving workloads built on the benchmarks of Sec. 3 with
+ * the parameter draws of Sec. 3.1.2 / DP-2): every admitted plan keeps its own
+ * state in its own device buffers; each stage of all unfinished plans runs as
+ * ONE persistent launch whose workgroups stride over the concatenated tiles
+ * of the instances, followed by one batched QoI/phi finalize. Per plan the
+ * arithmetic is that of sn_plan_run, so a plan's results are the same alone
+ * and in any mix (bit for bit).
+ *
+ * Ownership: the batch owns host state only. Its device tables live in a
+ * caller-provided workspace of sn_batch_workspace_bytes(opts) bytes (256-byte
+ * aligned, valid until sn_batch_destroy). Admitted plans stay owned by the
+ * caller and must not be run, rebound, re-initialised or destroyed while
+ * admitted. The batch never allocates device memory. */
+typedef struct sn_batch_opts {
+    int32_t max_instances;     /* slots, 1 .. 4096 */
+    int32_t max_steps_per_run; /* most steps one sn_batch_run takes, 1 .. 256 */
+    int32_t order, stepper, psi_dtype; /* every admitted plan must match */
+    int32_t rows_per_wave, waves_per_group; /* launch shape of every admitted
+                                             * plan (0 = library default) */
+    uint64_t hbm_budget_bytes; /* admitted plans' 2 psi_bytes + scratch_bytes
+                                * may not exceed this (0 = unlimited) */
+    int32_t use_graph;         /* 1: each run's launches are captured in a
+                                * hipGraph, replayed while the set and the
+                                * active pattern are unchanged */
+} sn_batch_opts;
+
+typedef struct sn_batch_info {
+    int32_t n_admitted;        /* occupied slots */
+    int32_t n_unfinished;      /* admitted plans with step < N_t */
+    uint64_t bytes_admitted;   /* sum of the admitted plans' footprints */
+    uint64_t hbm_budget_bytes;
+    int64_t launches;          /* batched stage launches issued so far */
+    int64_t graph_replays;     /* runs served by replaying a captured graph */
+} sn_batch_info;
+
+typedef struct sn_batch sn_batch;
+
+/* Workspace bytes for these options. SN_ERR_INVALID on bad options. */
+sn_status sn_batch_workspace_bytes(const sn_batch_opts *opts, uint64_t *bytes);
+
+/* Host-only set-up (plus one query of the current device's compute units). */
+sn_status sn_batch_create(const sn_batch_opts *opts, void *workspace, sn_batch **out);
+
+/* Footprint of a plan in HBM: 2 psi_bytes + scratch_bytes. */
+sn_status sn_plan_footprint(const sn_plan *plan, uint64_t *bytes);
+
+/* Admit a bound and initialised plan into a free slot. SN_ERR_BUSY when no
+ * slot is free or the budget would be exceeded; SN_ERR_INVALID when its order,
+ * stepper, storage type or launch shape differs from the batch's. Uploads the
+ * plan's launch tables (synchronous copy). */
+sn_status sn_batch_admit(sn_batch *batch, sn_plan *plan, int32_t *slot);
+
+/* Advance every admitted plan with step < N_t by min(n_steps, N_t - step)
+ * steps, 1 <= n_steps <= max_steps_per_run. Asynchronous on `stream`. */
+sn_status sn_batch_run(sn_batch *batch, int32_t n_steps, void *stream);
+
+/* Host view of a slot: done = (step == N_t). The QoIs of the plan come from
+ * sn_plan_qoi on the plan itself (synchronising). */
+sn_status sn_batch_status(const sn_batch *batch, int32_t slot, int32_t *done, int64_t *step);
+
+/* Free a slot; the plan is the caller's again (in whatever state it reached). */
+sn_status sn_batch_retire(sn_batch *batch, int32_t slot);
+
+sn_status sn_batch_get_info(const sn_batch *batch, sn_batch_info *out);
+
+void sn_batch_destroy(sn_batch *batch);
+
 const char *sn_status_str(sn_status s);
 const char *sn_last_error(void);
 

@@ -33,6 +33,8 @@ EXPORTED = [
     "sn_plan_init", "sn_plan_run", "sn_plan_run_unbounded", "sn_plan_qoi",
     "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_use_graph", "sn_plan_set_timing",
     "sn_plan_kernel_ms", "sn_plan_destroy", "sn_status_str", "sn_last_error",
+    "sn_batch_workspace_bytes", "sn_batch_create", "sn_plan_footprint", "sn_batch_admit", "sn_batch_run",
+    "sn_batch_status", "sn_batch_retire", "sn_batch_get_info", "sn_batch_destroy",
 ]
 
 _d = ctypes.c_double
@@ -69,6 +71,21 @@ class SnQoi(ctypes.Structure):
         ("int_mass", _d), ("int_source", _d), ("int_absorption", _d * MAX_TALLIES),
         ("int_outflow", _d * MAX_RECTS), ("int_inflow", _d * MAX_RECTS),
         ("balance_residual", _d), ("nonfinite", _i32),
+    ]
+
+
+class SnBatchOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_instances", _i32), ("max_steps_per_run", _i32), ("order", _i32), ("stepper", _i32),
+        ("psi_dtype", _i32), ("rows_per_wave", _i32), ("waves_per_group", _i32),
+        ("hbm_budget_bytes", ctypes.c_uint64), ("use_graph", _i32),
+    ]
+
+
+class SnBatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_admitted", _i32), ("n_unfinished", _i32), ("bytes_admitted", ctypes.c_uint64),
+        ("hbm_budget_bytes", ctypes.c_uint64), ("launches", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
     ]
 
 
@@ -109,6 +126,16 @@ def lib():
         L.sn_plan_kernel_ms.argtypes = [_vp, ctypes.POINTER(_d * 4), ctypes.POINTER(ctypes.c_int64 * 4)]
         L.sn_plan_destroy.argtypes = [_vp]
         L.sn_plan_destroy.restype = None
+        L.sn_batch_workspace_bytes.argtypes = [ctypes.POINTER(SnBatchOpts), ctypes.POINTER(ctypes.c_uint64)]
+        L.sn_batch_create.argtypes = [ctypes.POINTER(SnBatchOpts), _vp, PP]
+        L.sn_plan_footprint.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.sn_batch_admit.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
+        L.sn_batch_run.argtypes = [_vp, _i32, _vp]
+        L.sn_batch_status.argtypes = [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)]
+        L.sn_batch_retire.argtypes = [_vp, _i32]
+        L.sn_batch_get_info.argtypes = [_vp, ctypes.POINTER(SnBatchInfo)]
+        L.sn_batch_destroy.argtypes = [_vp]
+        L.sn_batch_destroy.restype = None
         L.sn_status_str.argtypes = [_i32]
         L.sn_status_str.restype = ctypes.c_char_p
         L.sn_last_error.argtypes = []

@@ -88,12 +88,15 @@ __global__ void __launch_bounds__(256) sn_ghost_fill_kernel(const GhostArgs a) {
 // Workgroups [nq, nq + n_phi_wg): phi = sum over groups of the stage's
 // partial scalar fluxes, in group order, for every interior cell (4 padded
 // columns per thread, ny * pitch / 4 threads).
-__global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs a) {
-    if ((int)blockIdx.x >= a.nq) {
+using FArgs = const __attribute__((address_space(4))) FinalizeArgs&;
+using FArgsPtr = const __attribute__((address_space(4))) FinalizeArgs*;
+
+__device__ __forceinline__ void finalize_block(FArgs a, int blk) {
+    if (blk >= a.nq) {
         // four consecutive padded columns per thread (16-byte aligned: the
         // pitch is a multiple of 16 elements); only interior cells are written
         const int per_row = a.pitch / 4;
-        const int64_t u = (int64_t)(blockIdx.x - a.nq) * 256 + threadIdx.x;
+        const int64_t u = (int64_t)(blk - a.nq) * 256 + threadIdx.x;
         if (u >= (int64_t)a.ny * per_row) return;
         const int j = (int)(u / per_row), c4 = (int)(u - (int64_t)j * per_row);
         const int64_t off = (int64_t)(j + kGhost) * a.pitch + 4 * c4;
@@ -130,7 +133,7 @@ __global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs
         }
         return;
     }
-    const int s = blockIdx.x;
+    const int s = blk;
     // eight independent accumulators per thread, combined in a fixed order
     const double* qp = a.qpart + (int64_t)s * a.n_wg;
     double acc8[8];
@@ -145,6 +148,7 @@ __global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs
     }
     double acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
     __shared__ double red[256];
+    __syncthreads();  // a previous block of a batched launch may still read red
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int m = 128; m >= 1; m >>= 1) {
@@ -156,6 +160,19 @@ __global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs
         a.inst[s] = tot;
         a.integ[s] += a.coef * tot;
         if (!isfinite(tot)) a.flags[0] = 1;
+    }
+}
+
+__global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs a) {
+    finalize_block(*(FArgsPtr)&a, blockIdx.x);
+}
+
+// Finalize of many instances in one persistent launch.
+__global__ void __launch_bounds__(256) sn_finalize_batch_kernel(const FinalizeBatch L) {
+    using ci32 = const __attribute__((address_space(4))) int32_t*;
+    for (int item = blockIdx.x; item < L.total; item += gridDim.x) {
+        const int j = find_instance(L.first, L.n_sel, item);
+        finalize_block(*(FArgsPtr)(L.args + ((ci32)L.sel)[j]), item - ((ci32)L.first)[j]);
     }
 }
 
@@ -183,6 +200,22 @@ hipError_t launch_stage(int order, int mode, int dtype, int rows, int waves, con
     if (order == 2)
         return dtype == 0 ? launch_stage_o2_f32(mode, rows, waves, a, s) : launch_stage_o2_bf16(mode, rows, waves, a, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_batch(int order, int mode, int dtype, int rows, int waves, const BatchLaunch& L, int grid,
+                              int max_rects, hipStream_t s) {
+    if (order == 1)
+        return dtype == 0 ? launch_batch_o1_f32(mode, rows, waves, L, grid, max_rects, s)
+                          : launch_batch_o1_bf16(mode, rows, waves, L, grid, max_rects, s);
+    if (order == 2)
+        return dtype == 0 ? launch_batch_o2_f32(mode, rows, waves, L, grid, max_rects, s)
+                          : launch_batch_o2_bf16(mode, rows, waves, L, grid, max_rects, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(sn_finalize_batch_kernel, dim3(grid), dim3(256), 0, s, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {

@@ -78,6 +78,27 @@ struct StageArgs {
     int32_t rect[kMaxRects][4];
 };
 
+// One batched launch over several instances (plans): the grid strides over
+// items 0 .. total-1; item i belongs to selected instance j with
+// first[j] <= i < first[j + 1] and is that instance's workgroup i - first[j].
+// The instance's arguments are args[sel[j]].
+struct BatchLaunch {
+    const StageArgs* args;
+    const int32_t* sel;    // [n_sel]
+    const int32_t* first;  // [n_sel + 1]
+    int32_t n_sel;
+    int32_t total;
+};
+
+struct FinalizeArgs;
+struct FinalizeBatch {
+    const FinalizeArgs* args;
+    const int32_t* sel;
+    const int32_t* first;
+    int32_t n_sel;
+    int32_t total;
+};
+
 struct GhostArgs {
     void* psi;
     const OrdConst* ord;
@@ -114,6 +135,11 @@ struct PhiInitArgs {
 hipError_t launch_stage(int order, int mode, int dtype, int rows_per_wave, int waves, const StageArgs& a,
                         hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// Batched forms (persistent grid of `grid` workgroups). Stage modes kUpdate
+// and kAverage only.
+hipError_t launch_stage_batch(int order, int mode, int dtype, int rows_per_wave, int waves, const BatchLaunch& L,
+                              int grid, int max_rects, hipStream_t s);
+hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s);
 hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s);
 hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s);
 bool supported_shape(int rows_per_wave, int waves);
@@ -123,5 +149,13 @@ hipError_t launch_stage_o1_f32(int mode, int rows, int waves, const StageArgs& a
 hipError_t launch_stage_o2_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o1_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o2_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
+hipError_t launch_batch_o1_f32(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
+                               hipStream_t s);
+hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
+                               hipStream_t s);
+hipError_t launch_batch_o1_bf16(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
+                                hipStream_t s);
+hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
+                                hipStream_t s);
 
 }  // namespace snk

@@ -1,0 +1,103 @@
+// sn_host.h -- host-side internals of libsnrt shared by the plan and batch
+// translation units: the plan object, error reporting, argument builders.
+// Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sn_device.h"
+#include "snrt.h"
+
+namespace snh {
+
+// Sets the thread's last-error text and returns s.
+sn_status fail(sn_status s, const char* fmt, ...);
+sn_status hip_fail(hipError_t e, const char* what);
+const char* last_error();
+
+#define HIP_TRY(expr, what)                                \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return snh::hip_fail(e_, what); \
+    } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace snh
+
+struct sn_plan {
+    // statement (copied)
+    int nx = 0, ny = 0, M = 0;
+    double h = 0;
+    std::vector<double> xi, eta, w;
+    std::vector<int32_t> mx, my;
+    std::vector<uint8_t> region;
+    std::vector<double> sa, ss, q;
+    std::vector<uint8_t> tally;
+    int n_regions = 0, n_tallies = 0, n_rects = 0;
+    int bc[4] = {0, 0, 0, 0};
+    double inflow[4] = {0, 0, 0, 0};
+    int order = 1, stepper = 0, dtype = 0;
+    double cfl = 0, t_end = 0;
+    int rects[snk::kMaxRects][4] = {};
+
+    // derived
+    int nt = 0;
+    double dt = 0;
+    int pitch = 0, ny_alloc = 0;
+    int64_t plane = 0, origin = 0;
+    int G = 1, Mg = 1, rows = 2, waves = 4;
+    int ntx = 0, nty = 0, n_wg = 0, nq = 0;
+    size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
+    size_t off_phi = 0, off_phi_part = 0, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
+           off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
+    double source = 0;  // (sum w) h^2 sum_cells Q
+    std::vector<snk::OrdConst> ord_h;
+    std::vector<snk::RegConst> reg_h;
+    std::vector<uint8_t> region_h;  // [ny][pitch]
+    std::vector<double> scale_h;
+
+    // device
+    char* psi[2] = {nullptr, nullptr};
+    char* scratch = nullptr;
+    bool bound = false, inited = false;
+    int64_t step = 0;
+    int cur = 0;  // buffer holding the current state
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    std::vector<int> ev_kind;
+    int ev_used = 0;
+    double kernel_ms[4] = {0, 0, 0, 0};
+    int64_t kernel_count[4] = {0, 0, 0, 0};
+
+    // membership of a batch (a plan in a batch is advanced only by it)
+    const sn_batch* batch = nullptr;
+
+    // graph replay
+    int graph_steps = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t graph_stream = nullptr;
+
+    template <typename P>
+    P* sp(size_t off) const { return reinterpret_cast<P*>(scratch + off); }
+};
+
+namespace snh {
+
+// Kernel arguments of one stage of plan P (see launch_stage_pair in
+// snrt_plan.cpp for the buffer roles of each kind).
+snk::StageArgs stage_args(const sn_plan* P, const char* in, const char* old, char* out);
+// Finalize arguments of a stage of P; kind 0 Euler, 1/2 Heun stages, -1 QoI only.
+snk::FinalizeArgs finalize_args(const sn_plan* P, int kind);
+
+}  // namespace snh

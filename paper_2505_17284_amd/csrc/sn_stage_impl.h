@@ -47,6 +47,12 @@
 
 namespace snk {
 
+// Stage arguments are read through the constant address space wherever they
+// live (the kernel-argument segment, or a device table of a batched launch):
+// uniform scalar loads, including the indexed rectangle table.
+using SArgs = const __attribute__((address_space(4))) StageArgs&;
+using SArgsPtr = const __attribute__((address_space(4))) StageArgs*;
+
 // ---------------------------------------------------------------- storage
 template <typename T>
 struct Store;
@@ -148,7 +154,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Face-QoI tags of one cell: bit (4 * kind + q) is set when the cell's face of
 // that kind (0 W, 1 E, 2 S, 3 N) lies on the boundary of rectangle q. Each
 // rectangle-boundary face is assigned to the cell inside the rectangle.
-__device__ __forceinline__ uint32_t face_tags(const StageArgs& a, int i, int j, bool valid) {
+__device__ __forceinline__ uint32_t face_tags(SArgs a, int i, int j, bool valid) {
     uint32_t tg = 0;
     if (!valid || j >= a.ny) return 0;
     for (int q = 0; q < a.n_rects; ++q) {
@@ -216,7 +222,7 @@ struct RowStage {
 };
 
 template <typename T, int TY, int W>
-__device__ __forceinline__ void stage_issue(const StageArgs& a, int k, int yw, int wave, const WaveCtx<TY>& w,
+__device__ __forceinline__ void stage_issue(SArgs a, int k, int yw, int wave, const WaveCtx<TY>& w,
                                             float2 (&pre)[RowStage<TY, W>::kPer]) {
     const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_in) + (size_t)k * w.planeb, w.planeb);
 #pragma unroll
@@ -238,7 +244,7 @@ __device__ __forceinline__ void stage_commit(float2 (*buf)[kWave], int wave, int
 
 // psi^n at the wave's own cells (Heun stage 2).
 template <typename T, int TY>
-__device__ __forceinline__ void load_old(const StageArgs& a, int k, const WaveCtx<TY>& w, float2 (&o)[TY]) {
+__device__ __forceinline__ void load_old(SArgs a, int k, const WaveCtx<TY>& w, float2 (&o)[TY]) {
     const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_old) + (size_t)k * w.planeb, w.planeb);
     const uint32_t row0 = (uint32_t)(w.y0 + kGhost) * w.pitchb;
 #pragma unroll
@@ -258,7 +264,7 @@ __device__ __forceinline__ void put_pair(char* p, size_t off, float2 v, bool v0,
 // gets the value in both layers. Lanes without a boundary cell carry the
 // dropped offset, so the stores need no branches.
 template <typename T, int TY, bool SX, bool SY>
-__device__ __forceinline__ void write_frame(const StageArgs& a, const OrdConst& o, int k, int j, uint32_t rowb,
+__device__ __forceinline__ void write_frame(SArgs a, const OrdConst& o, int k, int j, uint32_t rowb,
                                             rsrc_t rout, const WaveCtx<TY>& w, float2 v) {
     const char* out = static_cast<const char*>(a.psi_out);
     if (!SX) {  // leaves through W
@@ -298,7 +304,7 @@ __device__ __forceinline__ void write_frame(const StageArgs& a, const OrdConst& 
 // ---------------------------------------------------------------- one ordinate
 // Window row r holds grid row y0 - 2 + r; output row t is window row t + 2.
 template <int ORDER, int MODE, typename T, int TY, int W, bool SX, bool SY>
-__device__ __forceinline__ void stage_ordinate(const StageArgs& a, const OrdConst& o, int k, WaveCtx<TY>& w,
+__device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k, WaveCtx<TY>& w,
                                                const float2 (&win)[TY + 4], const float2 (&oldv)[TY],
                                                double* facc) {
     constexpr int D = SY ? 0 : 1;  // y-traces of output row t: Ry[t + 1 + D] (south), Ry[t + 2 + D] (north)
@@ -407,7 +413,7 @@ __device__ __forceinline__ void stage_ordinate(const StageArgs& a, const OrdCons
 using const_ord_ptr = const __attribute__((address_space(4))) OrdConst*;
 
 template <int ORDER, int MODE, typename T, int TY, int W>
-__device__ __forceinline__ void process_ordinate(const StageArgs& a, int k, WaveCtx<TY>& w,
+__device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
                                                  const float2 (&win)[TY + 4], const float2 (&oldv)[TY],
                                                  double* facc) {
     const const_ord_ptr q = (const_ord_ptr)a.ord + k;
@@ -428,22 +434,33 @@ __device__ __forceinline__ void process_ordinate(const StageArgs& a, int k, Wave
     }
 }
 
-// ---------------------------------------------------------------- stage kernel
+// ---------------------------------------------------------------- one workgroup tile
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of logical workgroups so halo rows and phi stay in its L2. The
+// ordinate groups of a tile are adjacent (ordering by tile row first measured
+// slower on the 700 x 700 lattice).
+__device__ __forceinline__ int xcd_contiguous(int b, int nwg) {
+    const int xcd = b & 7, q8 = b >> 3, per = nwg >> 3, rem = nwg & 7;
+    return xcd < rem ? xcd * (per + 1) + q8 : rem * (per + 1) + (xcd - rem) * per + q8;
+}
+
+template <int TY, int W>
+struct StageLds {
+    double red[W][kMaxQ];
+    float2 rows[2][RowStage<TY, W>::kRows][kWave];
+};
+
+// The work of logical workgroup `logical` of one stage launch: tile and
+// ordinate group, all ordinates of the group, epilogues. facc_all holds
+// 2 n_rects FP64 accumulators per thread.
 template <int ORDER, int MODE, typename T, int TY, int W>
-__global__ void __launch_bounds__(kWave * W) sn_stage_kernel(const StageArgs a) {
-    extern __shared__ double facc_all[];  // [2 n_rects][256] per-thread FP64 face accumulators
-    __shared__ double red[W][kMaxQ];
-    __shared__ float2 rows_lds[2][RowStage<TY, W>::kRows][kWave];
+__device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_all,
+                                           StageLds<TY, W>& lds) {
+    auto& red = lds.red;
+    auto& rows_lds = lds.rows;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of tiles so halo rows and phi stay in its L2. The
-    // ordinate groups of a tile are adjacent; ordering by tile row first
-    // measured slower on the 700 x 700 lattice.
-    const int nwg = gridDim.x, b = blockIdx.x;
-    const int xcd = b & 7, q8 = b >> 3, per = nwg >> 3, rem = nwg & 7;
-    const int logical = xcd < rem ? xcd * (per + 1) + q8 : rem * (per + 1) + (xcd - rem) * per + q8;
     const int g = logical % a.G;
     const int tile = logical / a.G;
     const int tx = tile % a.ntx;
@@ -609,7 +626,56 @@ __global__ void __launch_bounds__(kWave * W) sn_stage_kernel(const StageArgs a) 
         double tot = red[0][tid];
 #pragma unroll
         for (int ww = 1; ww < W; ++ww) tot += red[ww][tid];
-        a.qpart[(size_t)tid * a.n_wg + b] = tot;
+        a.qpart[(size_t)tid * a.n_wg + logical] = tot;
+    }
+}
+
+// ---------------------------------------------------------------- stage kernels
+// Occupancy each mode is compiled for (waves per SIMD): the update stage fits
+// 80 VGPRs (6 waves), the averaging stage keeps psi^n in flight too (5).
+template <int MODE, int TY>
+struct WavesPerEu {
+    static constexpr int value = TY > 2 ? 3 : (MODE == kUpdate ? 6 : (MODE == kAverage ? 5 : 8));
+};
+
+template <int ORDER, int MODE, typename T, int TY, int W>
+__global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, TY>::value)))
+sn_stage_kernel(const StageArgs a) {
+    extern __shared__ double facc_all[];  // [2 n_rects][kWave W] per-thread FP64 face accumulators
+    __shared__ StageLds<TY, W> lds;
+    stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, xcd_contiguous(blockIdx.x, gridDim.x), facc_all, lds);
+}
+
+// Index j of the selected instance holding item: first[j] <= item < first[j + 1].
+__device__ __forceinline__ int find_instance(const int32_t* first, int n, int item) {
+    using ci32 = const __attribute__((address_space(4))) int32_t*;
+    const ci32 f = (ci32)first;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (f[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One stage of many instances in one persistent launch: the grid strides over
+// the concatenated workgroup lists of the selected instances.
+template <int ORDER, int MODE, typename T, int TY, int W>
+__global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(WavesPerEu<kAverage, TY>::value)))
+sn_stage_batch_kernel(const BatchLaunch L) {
+    extern __shared__ double facc_all[];
+    __shared__ StageLds<TY, W> lds;
+    using ci32 = const __attribute__((address_space(4))) int32_t*;
+    const int pos = xcd_contiguous(blockIdx.x, gridDim.x);
+    for (int base = 0; base < L.total; base += gridDim.x) {
+        const int item = base + pos;
+        if (item >= L.total) break;  // workgroup-uniform; later rounds are past the end too
+        const int j = find_instance(L.first, L.n_sel, item);
+        const SArgsPtr a = (SArgsPtr)(L.args + ((ci32)L.sel)[j]);
+        const int local = item - ((ci32)L.first)[j];
+        __syncthreads();  // the previous item's LDS reads are done
+        stage_tile<ORDER, MODE, T, TY, W>(*a, local, facc_all, lds);
     }
 }
 
@@ -634,6 +700,35 @@ static hipError_t launch_stage_tu(int mode, int rows, int waves, const StageArgs
         if (mode == kUpdate) launch_w<ORDER, kUpdate, T, 4>(waves, a, s);
         else if (mode == kAverage) launch_w<ORDER, kAverage, T, 4>(waves, a, s);
         else launch_w<ORDER, kQoiOnly, T, 4>(waves, a, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Persistent batched launch: `grid` workgroups stride over L.total items;
+// max_rects sizes the per-thread face accumulators.
+template <int ORDER, int MODE, typename T, int TY>
+static void launch_batch_w(int waves, const BatchLaunch& L, int grid, int max_rects, hipStream_t s) {
+    const size_t lds_per_thread = (size_t)2 * max_rects * sizeof(double);
+    switch (waves) {
+    case 4: hipLaunchKernelGGL((sn_stage_batch_kernel<ORDER, MODE, T, TY, 4>), dim3(grid), dim3(kWave * 4), lds_per_thread * kWave * 4, s, L); break;
+    case 8: hipLaunchKernelGGL((sn_stage_batch_kernel<ORDER, MODE, T, TY, 8>), dim3(grid), dim3(kWave * 8), lds_per_thread * kWave * 8, s, L); break;
+    default: hipLaunchKernelGGL((sn_stage_batch_kernel<ORDER, MODE, T, TY, 16>), dim3(grid), dim3(kWave * 16), lds_per_thread * kWave * 16, s, L); break;
+    }
+}
+
+template <int ORDER, typename T>
+static hipError_t launch_batch_tu(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
+                                  hipStream_t s) {
+    if (waves != 4 && waves != 8 && waves != 16) return hipErrorInvalidValue;
+    if (mode != kUpdate && mode != kAverage) return hipErrorInvalidValue;
+    if (rows == 2) {
+        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 2>(waves, L, grid, max_rects, s);
+        else launch_batch_w<ORDER, kAverage, T, 2>(waves, L, grid, max_rects, s);
+    } else if (rows == 4) {
+        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 4>(waves, L, grid, max_rects, s);
+        else launch_batch_w<ORDER, kAverage, T, 4>(waves, L, grid, max_rects, s);
     } else {
         return hipErrorInvalidValue;
     }

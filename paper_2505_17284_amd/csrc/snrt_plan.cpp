@@ -12,14 +12,15 @@
 #include <string>
 #include <vector>
 
-#include "sn_device.h"
-#include "snrt.h"
+#include "sn_host.h"
 
 using namespace snk;
 
-namespace {
+namespace snh {
 
+namespace {
 thread_local std::string g_err;
+}
 
 sn_status fail(sn_status s, const char* fmt, ...) {
     char buf[512];
@@ -35,74 +36,11 @@ sn_status hip_fail(hipError_t e, const char* what) {
     return fail(SN_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                       \
-    do {                                          \
-        hipError_t e_ = (expr);                   \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+const char* last_error() { return g_err.c_str(); }
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
+}  // namespace snh
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-}  // namespace
-
-struct sn_plan {
-    // statement (copied)
-    int nx = 0, ny = 0, M = 0;
-    double h = 0;
-    std::vector<double> xi, eta, w;
-    std::vector<int32_t> mx, my;
-    std::vector<uint8_t> region;
-    std::vector<double> sa, ss, q;
-    std::vector<uint8_t> tally;
-    int n_regions = 0, n_tallies = 0, n_rects = 0;
-    int bc[4] = {0, 0, 0, 0};
-    double inflow[4] = {0, 0, 0, 0};
-    int order = 1, stepper = 0, dtype = 0;
-    double cfl = 0, t_end = 0;
-    int rects[kMaxRects][4] = {};
-
-    // derived
-    int nt = 0;
-    double dt = 0;
-    int pitch = 0, ny_alloc = 0;
-    int64_t plane = 0, origin = 0;
-    int G = 1, Mg = 1, rows = 2, waves = 8;
-    int ntx = 0, nty = 0, n_wg = 0, nq = 0;
-    size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
-    size_t off_phi = 0, off_phi_part = 0, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
-           off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
-    double source = 0;  // (sum w) h^2 sum_cells Q
-    std::vector<OrdConst> ord_h;
-    std::vector<RegConst> reg_h;
-    std::vector<uint8_t> region_h;  // [ny][pitch]
-    std::vector<double> scale_h;
-
-    // device
-    char* psi[2] = {nullptr, nullptr};
-    char* scratch = nullptr;
-    bool bound = false, inited = false;
-    int64_t step = 0;
-    int cur = 0;  // buffer holding the current state
-
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev_start, ev_stop;
-    std::vector<int> ev_kind;
-    int ev_used = 0;
-    double kernel_ms[4] = {0, 0, 0, 0};
-    int64_t kernel_count[4] = {0, 0, 0, 0};
-
-    // graph replay
-    int graph_steps = 0;
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
-    hipStream_t graph_stream = nullptr;
-
-    template <typename P>
-    P* sp(size_t off) const { return reinterpret_cast<P*>(scratch + off); }
-};
+using namespace snh;
 
 namespace {
 
@@ -335,7 +273,9 @@ sn_status derive(sn_plan* P, int group_size, int rows, int waves) {
     return SN_OK;
 }
 
-StageArgs stage_args(const sn_plan* P, int mode, const char* in, const char* old, char* out) {
+}  // namespace
+
+StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, char* out) {
     StageArgs a{};
     a.psi_in = in;
     a.psi_old = old;
@@ -362,9 +302,31 @@ StageArgs stage_args(const sn_plan* P, int mode, const char* in, const char* old
     for (int s = 0; s < 4; ++s) a.bc[s] = P->bc[s];
     for (int r = 0; r < P->n_rects; ++r)
         for (int e = 0; e < 4; ++e) a.rect[r][e] = P->rects[r][e];
-    (void)mode;
     return a;
 }
+
+FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
+    FinalizeArgs f{};
+    f.phi_part = P->sp<float>(P->off_phi_part);
+    f.phi = P->sp<float>(P->off_phi);
+    f.plane = P->plane;
+    f.nx = P->nx;
+    f.ny = P->ny;
+    f.pitch = P->pitch;
+    f.G = P->G;
+    f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
+    f.qpart = P->sp<double>(P->off_qpart);
+    f.scale = P->sp<double>(P->off_scale);
+    f.inst = P->sp<double>(P->off_inst);
+    f.integ = P->sp<double>(P->off_integ);
+    f.flags = P->sp<int32_t>(P->off_flags);
+    f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
+    f.n_wg = P->n_wg;
+    f.nq = P->nq;
+    return f;
+}
+
+namespace {
 
 GhostArgs ghost_args(const sn_plan* P, char* psi) {
     GhostArgs ga{};
@@ -407,7 +369,7 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
         out = P->psi[0];
     }
     if (kind < 0) out = nullptr;
-    StageArgs a = stage_args(P, mode, in, old, out);
+    StageArgs a = stage_args(P, in, old, out);
     const bool timed = P->timing && allow_timing && kind >= 0;
     if (timed) {
         if (P->ev_used == (int)P->ev_start.size()) {
@@ -422,23 +384,7 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
         P->ev_kind[P->ev_used] = kind;
         P->ev_used++;
     }
-    FinalizeArgs f{};
-    f.phi_part = P->sp<float>(P->off_phi_part);
-    f.phi = P->sp<float>(P->off_phi);
-    f.plane = P->plane;
-    f.nx = P->nx;
-    f.ny = P->ny;
-    f.pitch = P->pitch;
-    f.G = P->G;
-    f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
-    f.qpart = P->sp<double>(P->off_qpart);
-    f.scale = P->sp<double>(P->off_scale);
-    f.inst = P->sp<double>(P->off_inst);
-    f.integ = P->sp<double>(P->off_integ);
-    f.flags = P->sp<int32_t>(P->off_flags);
-    f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
-    f.n_wg = P->n_wg;
-    f.nq = P->nq;
+    const FinalizeArgs f = finalize_args(P, kind);
     HIP_TRY(launch_finalize(f, s), "finalize launch");
     return SN_OK;
 }
@@ -470,6 +416,7 @@ void drop_graph(sn_plan* P) {
 
 sn_status run_steps(sn_plan* P, int n, hipStream_t s) {
     if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    if (P->batch) return fail(SN_ERR_STATE, "plan is admitted to a batch; the batch advances it");
     if (n <= 0) return SN_OK;
     int done = 0;
     if (P->graph_steps > 0 && !P->timing) {
@@ -508,7 +455,7 @@ sn_status run_steps(sn_plan* P, int n, hipStream_t s) {
 
 extern "C" {
 
-const char* sn_last_error(void) { return g_err.c_str(); }
+const char* sn_last_error(void) { return snh::last_error(); }
 
 const char* sn_status_str(sn_status s) {
     switch (s) {
@@ -573,6 +520,7 @@ sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
 
 sn_status sn_plan_bind(sn_plan* P, void* psi_a, void* psi_b, void* scratch) {
     if (!P || !psi_a || !psi_b || !scratch) return fail(SN_ERR_INVALID, "NULL argument");
+    if (P->batch) return fail(SN_ERR_STATE, "plan is admitted to a batch");
     const uintptr_t pa = (uintptr_t)psi_a, pb = (uintptr_t)psi_b, ps = (uintptr_t)scratch;
     if ((pa | pb | ps) & 255) return fail(SN_ERR_INVALID, "device buffers must be 256-byte aligned");
     auto overlap = [](uintptr_t a, size_t na, uintptr_t b, size_t nb) { return a < b + nb && b < a + na; };
@@ -590,6 +538,7 @@ sn_status sn_plan_bind(sn_plan* P, void* psi_a, void* psi_b, void* scratch) {
 
 sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
+    if (P->batch) return fail(SN_ERR_STATE, "plan is admitted to a batch");
     if (!P->bound) return fail(SN_ERR_STATE, "plan not bound");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_ord), P->ord_h.data(), P->M * sizeof(OrdConst),

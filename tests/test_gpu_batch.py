@@ -1,0 +1,211 @@
+"""Batched solves (sn_batch_*): one persistent launch per stage for many
+problems of uneven sizes.
+
+Per problem the arithmetic of the batched kernels is that of the single-plan
+path, so every problem's state and QoIs must be bit-identical alone and in any
+mix, whatever the admission order, window length or graph replay; against the
+oracle they meet the single-plan tolerances.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+from tests.parity import compare_field, compare_qoi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bt():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17284_amd import batch, solver
+
+    return batch, solver
+
+
+def _mix(order=2, stepper=I.HEUN, dtype="f32"):
+    """Uneven grids, ordinate counts, rectangle counts, boundary kinds and end times."""
+    refl = (I.BC_REFLECT,) * 4
+    mixed = (I.BC_REFLECT, I.BC_INFLOW, I.BC_INFLOW, I.BC_REFLECT)
+    return [
+        I.lattice(70, 32, order=order, stepper=stepper, psi_dtype=dtype),
+        I.random_materials(61, 17, 4, seed=1, M=64, order=order, stepper=stepper, bc=mixed,
+                           inflow=(0.0, 0.7, 0.3, 0.0), t_end=0.3, psi_dtype=dtype),
+        I.random_materials(130, 37, 5, seed=2, M=32, order=order, stepper=stepper, bc=refl, t_end=0.45,
+                           rects=[(0, 0, 130, 37)], psi_dtype=dtype),
+        I.random_materials(9, 1, 2, seed=3, M=32, order=order, stepper=stepper, t_end=0.2, rects=[],
+                           psi_dtype=dtype),
+        I.cavity(52, 32, order=order, stepper=stepper, t_end=0.4, psi_dtype=dtype),
+    ]
+
+
+def _same(a, b, what):
+    assert np.array_equal(a["psi"], b["psi"]), f"{what}: psi differs"
+    assert np.array_equal(a["phi"], b["phi"]), f"{what}: phi differs"
+    assert a["qoi"] == b["qoi"], f"{what}: QoIs differ"
+    assert a["qoi_int"] == b["qoi_int"], f"{what}: integrated QoIs differ"
+    assert a["nt"] == b["nt"]
+
+
+def _alone(solver, problems):
+    out = []
+    for p in problems:
+        print(f"[case] alone {p.name} n=({p.nx},{p.ny}) M={p.M}", flush=True)
+        out.append(solver.solve(p, return_psi=True, rows_per_wave=2, waves_per_group=4))
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("window", [1, 7])
+def test_batch_bit_identical_to_alone(bt, use_graph, window):
+    batch, solver = bt
+    probs = _mix()
+    alone = _alone(solver, probs)
+    print(f"[case] batch graph={use_graph} window={window}", flush=True)
+    b = batch.Batch(max_instances=8, steps_per_run=window, use_graph=use_graph)
+    try:
+        slots = [b.admit(p) for p in probs]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            assert b.status(s) == (True, a["nt"])
+            _same(b.result(s, psi=True), a, p.name)
+        info = b.info()
+        if use_graph and window == 1:
+            assert info["graph_replays"] > 0, info
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("order,stepper", [(1, I.EULER), (2, I.EULER), (1, I.HEUN)])
+def test_batch_other_schemes(bt, order, stepper):
+    batch, solver = bt
+    probs = _mix(order=order, stepper=stepper)[:4]
+    alone = _alone(solver, probs)
+    res = batch.solve_all(probs, steps_per_run=5)
+    for p, r, a in zip(probs, res, alone):
+        assert r["qoi"] == a["qoi"] and r["qoi_int"] == a["qoi_int"], p.name
+    b = batch.Batch(order=order, stepper=stepper, max_instances=4, steps_per_run=3)
+    try:
+        slots = [b.admit(p) for p in probs]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            _same(b.result(s, psi=True), a, p.name)
+    finally:
+        b.close()
+
+
+def test_batch_bf16_bit_identical(bt):
+    batch, solver = bt
+    probs = _mix(dtype="bf16")[:3]
+    alone = _alone(solver, probs)
+    b = batch.Batch(psi_dtype="bf16", max_instances=3, steps_per_run=4)
+    try:
+        slots = [b.admit(p) for p in probs]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            _same(b.result(s, psi=True), a, p.name)
+    finally:
+        b.close()
+
+
+def test_batch_against_oracle(bt, orc):
+    batch, _ = bt
+    probs = _mix()[1:4]
+    psi0s = [I.random_state(p, 11 + i, "smooth") for i, p in enumerate(probs)]
+    b = batch.Batch(max_instances=3, steps_per_run=2)
+    try:
+        slots = [b.admit(p, psi0=q) for p, q in zip(probs, psi0s)]
+        b.run(2)
+        for p, s, q in zip(probs, slots, psi0s):
+            print(f"[case] oracle {p.name}", flush=True)
+            g = b.result(s, psi=True)
+            o = orc.solve(p, steps=2, psi0=q)
+            oi, oint = dict(zip(o["names"], o["qoi"])), dict(zip(o["names"], o["qoi_int"]))
+            ok, rep = compare_qoi(g["qoi"], g["qoi_int"], oi, oint)
+            assert ok, rep
+            okf, repf = compare_field(g["psi"], o["psi"], 4)
+            assert okf, repf
+    finally:
+        b.close()
+
+
+def test_continuous_admission_and_retirement(bt):
+    """Problems admitted while others are mid-run, finished ones retired and
+    their slots and memory reused: every result equals the problem alone."""
+    batch, solver = bt
+    probs = _mix() + [I.lattice(40, 32, order=2, stepper=I.HEUN, t_end=0.8),
+                      I.random_materials(33, 29, 3, seed=9, M=64, t_end=0.35)]
+    alone = _alone(solver, probs)
+    budget = 2 * max(batch.footprint(p) for p in probs) + min(batch.footprint(p) for p in probs)
+    b = batch.Batch(max_instances=3, steps_per_run=4, hbm_budget_bytes=budget)
+    try:
+        pending = list(range(len(probs)))
+        slot_of = {}
+        results = {}
+        rounds = 0
+        while pending or b.plans:
+            while pending and b.fits(probs[pending[0]]):
+                i = pending.pop(0)
+                slot_of[b.admit(probs[i])] = i
+            b.run()
+            rounds += 1
+            for s in b.done_slots():
+                i = slot_of.pop(s)
+                results[i] = b.result(s, psi=True)
+                b.retire(s)
+            assert rounds < 10000
+        for i, p in enumerate(probs):
+            _same(results[i], alone[i], p.name)
+    finally:
+        b.close()
+
+
+def test_budget_and_slots_refuse_admission(bt):
+    batch, _ = bt
+    p = I.lattice(70, 32, order=2, stepper=I.HEUN)
+    fp = batch.footprint(p)
+    b = batch.Batch(max_instances=4, hbm_budget_bytes=fp + fp // 2)
+    try:
+        s0 = b.admit(p)
+        with pytest.raises(batch.Busy):
+            b.admit(p)
+        b.retire(s0)
+        b.admit(p)
+    finally:
+        b.close()
+    b = batch.Batch(max_instances=1)
+    try:
+        b.admit(p)
+        with pytest.raises(batch.Busy):
+            b.admit(p)
+    finally:
+        b.close()
+
+
+def test_admitted_plan_cannot_run_alone(bt):
+    batch, solver = bt
+    p = I.lattice(70, 32, order=2, stepper=I.HEUN)
+    b = batch.Batch(max_instances=1)
+    try:
+        s = b.admit(p)
+        with pytest.raises(solver.SnError):
+            b.plans[s].run(1)
+    finally:
+        b.close()
+
+
+def test_mismatched_plan_rejected(bt):
+    batch, _ = bt
+    b = batch.Batch(max_instances=2)
+    try:
+        with pytest.raises(batch.SnError):
+            b.admit(I.lattice(70, 32, order=1, stepper=I.EULER))
+    finally:
+        b.close()
