@@ -11,6 +11,10 @@ Prints one JSON line. `value` = cell-ordinate updates per second (one update
 = one (cell, ordinate) advanced one full time step). `roofline` describes the
 dominant kernel (Heun stage 2) against 8 TB/s; `cpu_baseline` times the FP64
 oracle on a bounded sample of the same workload on the host cores.
+`batched_uq` runs 256 lattice draws (grid side 140..560, 64..256 ordinates)
+as one batch and one at a time; `serving` feeds Poisson arrivals of mixed
+lattice / cavity requests to the continuous-batching loop and to the
+one-at-a-time path and reports p50/p99 latency and solves/s for both.
 """
 
 import argparse
@@ -104,6 +108,12 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--uq", type=int, default=256,
+                    help="instances of the batched UQ workload (0 skips it)")
+    ap.add_argument("--serving-requests", type=int, default=16,
+                    help="requests of the serving comparison (0 skips it)")
+    ap.add_argument("--serving-load", type=float, default=0.9,
+                    help="arrival rate as a fraction of the one-at-a-time capacity")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -189,6 +199,15 @@ def main():
         torch.cuda.synchronize()
         line["calibration_copy_bytes"] = n
         del src, dst
+    from paper_2505_17284_amd import serve
+
+    if args.uq:
+        print(f"[bench] batched UQ: {args.uq} lattice draws", file=sys.stderr, flush=True)
+        line["batched_uq"] = serve.uq(args.uq, verbose=True)
+    if args.serving_requests:
+        print(f"[bench] serving: {args.serving_requests} requests at load {args.serving_load}",
+              file=sys.stderr, flush=True)
+        line["serving"] = serve.sweep(args.serving_requests, rates=(args.serving_load,), verbose=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(line), flush=True)

@@ -234,6 +234,15 @@ typedef struct sn_batch_opts {
     int32_t use_graph;         /* 1: each run's launches are captured in a
                                 * hipGraph, replayed while the set and the
                                 * active pattern are unchanged */
+    int32_t workgroups_per_cu; /* stage launches: 0 = one workgroup per tile
+                                * (default), > 0 = a persistent grid of that
+                                * many workgroups per compute unit striding
+                                * over the tiles, -1 = a persistent grid of as
+                                * many as are resident at once */
+    uint64_t cache_group_bytes; /* plans whose two psi buffers fit this size
+                                 * are packed into groups of at most this many
+                                 * bytes that take their steps of a run back to
+                                 * back (cache reuse); 0 = 64 MiB */
 } sn_batch_opts;
 
 typedef struct sn_batch_info {
@@ -265,6 +274,12 @@ sn_status sn_batch_admit(sn_batch *batch, sn_plan *plan, int32_t *slot);
 /* Advance every admitted plan with step < N_t by min(n_steps, N_t - step)
  * steps, 1 <= n_steps <= max_steps_per_run. Asynchronous on `stream`. */
 sn_status sn_batch_run(sn_batch *batch, int32_t n_steps, void *stream);
+
+/* Per-slot step quota: in every later sn_batch_run the slot advances at most
+ * `steps` steps (1 .. max_steps_per_run; 0 removes the quota). A scheduler
+ * uses it to share the GPU by work rather than by steps (cheap problems take
+ * more steps per run than expensive ones). */
+sn_status sn_batch_set_steps(sn_batch *batch, int32_t slot, int32_t steps);
 
 /* Host view of a slot: done = (step == N_t). The QoIs of the plan come from
  * sn_plan_qoi on the plan itself (synchronising). */

@@ -34,7 +34,7 @@ EXPORTED = [
     "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_use_graph", "sn_plan_set_timing",
     "sn_plan_kernel_ms", "sn_plan_destroy", "sn_status_str", "sn_last_error",
     "sn_batch_workspace_bytes", "sn_batch_create", "sn_plan_footprint", "sn_batch_admit", "sn_batch_run",
-    "sn_batch_status", "sn_batch_retire", "sn_batch_get_info", "sn_batch_destroy",
+    "sn_batch_set_steps", "sn_batch_status", "sn_batch_retire", "sn_batch_get_info", "sn_batch_destroy",
 ]
 
 _d = ctypes.c_double
@@ -78,7 +78,8 @@ class SnBatchOpts(ctypes.Structure):
     _fields_ = [
         ("max_instances", _i32), ("max_steps_per_run", _i32), ("order", _i32), ("stepper", _i32),
         ("psi_dtype", _i32), ("rows_per_wave", _i32), ("waves_per_group", _i32),
-        ("hbm_budget_bytes", ctypes.c_uint64), ("use_graph", _i32),
+        ("hbm_budget_bytes", ctypes.c_uint64), ("use_graph", _i32), ("workgroups_per_cu", _i32),
+        ("cache_group_bytes", ctypes.c_uint64),
     ]
 
 
@@ -131,6 +132,7 @@ def lib():
         L.sn_plan_footprint.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64)]
         L.sn_batch_admit.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
         L.sn_batch_run.argtypes = [_vp, _i32, _vp]
+        L.sn_batch_set_steps.argtypes = [_vp, _i32, _i32]
         L.sn_batch_status.argtypes = [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)]
         L.sn_batch_retire.argtypes = [_vp, _i32]
         L.sn_batch_get_info.argtypes = [_vp, ctypes.POINTER(SnBatchInfo)]

@@ -38,13 +38,15 @@ def footprint(problem, rows_per_wave: int = 0, waves_per_group: int = 0, group_s
 class Batch:
     def __init__(self, order: int = 2, stepper: int = 1, psi_dtype: str = "f32", max_instances: int = 256,
                  steps_per_run: int = 16, rows_per_wave: int = 2, waves_per_group: int = 4,
-                 hbm_budget_bytes: int = 0, use_graph: bool = True, device: str = "cuda:0"):
+                 hbm_budget_bytes: int = 0, use_graph: bool = True, workgroups_per_cu: int = 0,
+                 cache_group_bytes: int = 0, device: str = "cuda:0"):
         torch = solver._torch()
         self.device = torch.device(device)
         self.opts = SnBatchOpts(max_instances=max_instances, max_steps_per_run=steps_per_run, order=order,
                                 stepper=stepper, psi_dtype=SN_BF16 if psi_dtype == "bf16" else SN_F32,
                                 rows_per_wave=rows_per_wave, waves_per_group=waves_per_group,
-                                hbm_budget_bytes=hbm_budget_bytes, use_graph=1 if use_graph else 0)
+                                hbm_budget_bytes=hbm_budget_bytes, use_graph=1 if use_graph else 0,
+                                workgroups_per_cu=workgroups_per_cu, cache_group_bytes=cache_group_bytes)
         self.psi_dtype = psi_dtype
         self.steps_per_run = steps_per_run
         nbytes = ctypes.c_uint64()
@@ -99,6 +101,10 @@ class Batch:
         n = self.steps_per_run if n_steps is None else int(n_steps)
         check(lib().sn_batch_run(self.h, n, self.stream), "sn_batch_run")
 
+    def set_steps(self, slot: int, steps: int):
+        """Most steps the slot takes per run (0 = no quota)."""
+        check(lib().sn_batch_set_steps(self.h, slot, int(steps)), "sn_batch_set_steps")
+
     def status(self, slot: int):
         done = ctypes.c_int32()
         step = ctypes.c_int64()
@@ -118,10 +124,10 @@ class Batch:
         check(lib().sn_batch_get_info(self.h, ctypes.byref(info)), "sn_batch_get_info")
         return {f: getattr(info, f) for f, _ in SnBatchInfo._fields_}
 
-    def result(self, slot: int, psi: bool = False) -> dict:
+    def result(self, slot: int, psi: bool = False, allow_nonfinite: bool = False) -> dict:
         """QoIs of a slot's current state (synchronising), like solver.solve."""
         plan = self.plans[slot]
-        r = plan.qoi()
+        r = plan.qoi(allow_nonfinite=allow_nonfinite)
         r["nt"], r["dt"] = plan.n_steps, plan.dt
         if psi:
             r["psi"] = plan.psi()

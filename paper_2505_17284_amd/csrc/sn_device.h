@@ -135,10 +135,12 @@ struct PhiInitArgs {
 hipError_t launch_stage(int order, int mode, int dtype, int rows_per_wave, int waves, const StageArgs& a,
                         hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-// Batched forms (persistent grid of `grid` workgroups). Stage modes kUpdate
-// and kAverage only.
+// Batched forms. Stage: wgs_per_cu == 0 one workgroup per item, > 0 a
+// persistent grid of that many workgroups per CU, < 0 a persistent grid of the
+// resident capacity; modes kUpdate and kAverage only. Finalize: a persistent
+// grid of `grid`.
 hipError_t launch_stage_batch(int order, int mode, int dtype, int rows_per_wave, int waves, const BatchLaunch& L,
-                              int grid, int max_rects, hipStream_t s);
+                              int wgs_per_cu, int cus, int max_rects, hipStream_t s);
 hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s);
 hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s);
 hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s);
@@ -149,13 +151,13 @@ hipError_t launch_stage_o1_f32(int mode, int rows, int waves, const StageArgs& a
 hipError_t launch_stage_o2_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o1_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o2_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
-hipError_t launch_batch_o1_f32(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
-                               hipStream_t s);
-hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
-                               hipStream_t s);
-hipError_t launch_batch_o1_bf16(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
-                                hipStream_t s);
-hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
-                                hipStream_t s);
+hipError_t launch_batch_o1_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s);
+hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s);
+hipError_t launch_batch_o1_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s);
+hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s);
 
 }  // namespace snk

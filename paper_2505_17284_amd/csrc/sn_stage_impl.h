@@ -706,29 +706,55 @@ static hipError_t launch_stage_tu(int mode, int rows, int waves, const StageArgs
     return hipGetLastError();
 }
 
-// Persistent batched launch: `grid` workgroups stride over L.total items;
-// max_rects sizes the per-thread face accumulators.
+// Batched launch. wgs_per_cu == 0: one workgroup per item; > 0: a persistent
+// grid of that many workgroups per compute unit strides over the L.total
+// items; < 0: as many as are resident at once (occupancy of this kernel).
+template <typename K>
+static int batch_grid(K kernel, int threads, size_t lds, int total, int wgs_per_cu, int cus, int* cache) {
+    if (wgs_per_cu == 0) return total > 0 ? total : 1;
+    int per = wgs_per_cu;
+    if (per < 0) {
+        if (*cache <= 0) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) nb = 1;
+            *cache = nb;
+        }
+        per = *cache;
+    }
+    const long g = (long)per * cus;
+    return (int)(g < total ? g : (total > 0 ? total : 1));
+}
+
+template <int ORDER, int MODE, typename T, int TY, int W>
+static void launch_batch_shape(const BatchLaunch& L, int wgs_per_cu, int cus, int max_rects, hipStream_t s) {
+    static int resident[kMaxRects + 1] = {};  // per face-accumulator size, filled on first use
+    const size_t lds = (size_t)2 * max_rects * sizeof(double) * kWave * W;
+    auto kern = sn_stage_batch_kernel<ORDER, MODE, T, TY, W>;
+    const int grid = batch_grid(kern, kWave * W, lds, L.total, wgs_per_cu, cus, &resident[max_rects]);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * W), lds, s, L);
+}
+
 template <int ORDER, int MODE, typename T, int TY>
-static void launch_batch_w(int waves, const BatchLaunch& L, int grid, int max_rects, hipStream_t s) {
-    const size_t lds_per_thread = (size_t)2 * max_rects * sizeof(double);
+static void launch_batch_w(int waves, const BatchLaunch& L, int wgs_per_cu, int cus, int max_rects, hipStream_t s) {
     switch (waves) {
-    case 4: hipLaunchKernelGGL((sn_stage_batch_kernel<ORDER, MODE, T, TY, 4>), dim3(grid), dim3(kWave * 4), lds_per_thread * kWave * 4, s, L); break;
-    case 8: hipLaunchKernelGGL((sn_stage_batch_kernel<ORDER, MODE, T, TY, 8>), dim3(grid), dim3(kWave * 8), lds_per_thread * kWave * 8, s, L); break;
-    default: hipLaunchKernelGGL((sn_stage_batch_kernel<ORDER, MODE, T, TY, 16>), dim3(grid), dim3(kWave * 16), lds_per_thread * kWave * 16, s, L); break;
+    case 4: launch_batch_shape<ORDER, MODE, T, TY, 4>(L, wgs_per_cu, cus, max_rects, s); break;
+    case 8: launch_batch_shape<ORDER, MODE, T, TY, 8>(L, wgs_per_cu, cus, max_rects, s); break;
+    default: launch_batch_shape<ORDER, MODE, T, TY, 16>(L, wgs_per_cu, cus, max_rects, s); break;
     }
 }
 
 template <int ORDER, typename T>
-static hipError_t launch_batch_tu(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
-                                  hipStream_t s) {
+static hipError_t launch_batch_tu(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                                  int max_rects, hipStream_t s) {
     if (waves != 4 && waves != 8 && waves != 16) return hipErrorInvalidValue;
     if (mode != kUpdate && mode != kAverage) return hipErrorInvalidValue;
+    if (max_rects < 0 || max_rects > kMaxRects) return hipErrorInvalidValue;
     if (rows == 2) {
-        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 2>(waves, L, grid, max_rects, s);
-        else launch_batch_w<ORDER, kAverage, T, 2>(waves, L, grid, max_rects, s);
+        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 2>(waves, L, wgs_per_cu, cus, max_rects, s);
+        else launch_batch_w<ORDER, kAverage, T, 2>(waves, L, wgs_per_cu, cus, max_rects, s);
     } else if (rows == 4) {
-        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 4>(waves, L, grid, max_rects, s);
-        else launch_batch_w<ORDER, kAverage, T, 4>(waves, L, grid, max_rects, s);
+        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 4>(waves, L, wgs_per_cu, cus, max_rects, s);
+        else launch_batch_w<ORDER, kAverage, T, 4>(waves, L, wgs_per_cu, cus, max_rects, s);
     } else {
         return hipErrorInvalidValue;
     }

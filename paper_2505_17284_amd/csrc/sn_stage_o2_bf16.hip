@@ -7,9 +7,9 @@ hipError_t launch_stage_o2_bf16(int mode, int rows, int waves, const StageArgs& 
     return launch_stage_tu<2, uint16_t>(mode, rows, waves, a, s);
 }
 
-hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int grid, int max_rects,
-                               hipStream_t s) {
-    return launch_batch_tu<2, uint16_t>(mode, rows, waves, L, grid, max_rects, s);
+hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s) {
+    return launch_batch_tu<2, uint16_t>(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
 }
 
 }  // namespace snk

@@ -7,13 +7,14 @@
 //   stage   [max_instances][2] StageArgs: Heun stage 1 / stage 2, or Euler
 //                                         from buffer A / from buffer B
 //   final   [max_instances]    FinalizeArgs
-//   run     [max_steps][stage launches per step] x (stage sel, stage first,
-//                                         finalize first, finalize sel)
+//   run     launch records (stage sel, stage first, finalize first,
+//           finalize sel) of every launch of one run
 // A run of K steps is planned entirely on the host: which plans are still
 // unfinished at each step is known from their step counters, so every launch
-// gets its own instance list and no device-side bookkeeping is needed. The
-// launches of a run are captured into a hipGraph and replayed as long as the
-// admitted set and the active pattern repeat.
+// gets its own instance list and no device-side bookkeeping is needed. Small
+// plans are grouped so that a group's steps run out of the Infinity Cache.
+// The launches of a run are captured into a hipGraph and replayed as long as
+// the admitted set and the active pattern repeat.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,10 +30,11 @@ using namespace snh;
 struct sn_batch {
     sn_batch_opts o{};
     char* ws = nullptr;
-    size_t off_stage = 0, off_final = 0, off_run = 0, run_launch_ints = 0;
+    size_t off_stage = 0, off_final = 0, off_run = 0, run_ints = 0;
     int launches_per_step = 0;  // stage launches per step (1 Euler, 2 Heun)
     int cus = 0;
     std::vector<sn_plan*> slot;  // nullptr = free
+    std::vector<int32_t> quota;  // per slot: most steps per run (0 = none)
     uint64_t bytes_admitted = 0;
     int64_t launches = 0, graph_replays = 0;
     uint64_t epoch = 0;  // changes with every admission or retirement
@@ -68,11 +70,16 @@ sn_status check_opts(const sn_batch_opts* o) {
     const int waves = o->waves_per_group ? o->waves_per_group : 4;
     if (!supported_shape(rows, waves))
         return fail(SN_ERR_UNSUPPORTED, "launch shape rows_per_wave %d, waves %d not compiled", rows, waves);
+    if (o->workgroups_per_cu < -1 || o->workgroups_per_cu > 64)
+        return fail(SN_ERR_INVALID, "workgroups_per_cu = %d out of range [-1, 64]", o->workgroups_per_cu);
     return SN_OK;
 }
 
-// Workspace layout for the options.
-void layout(const sn_batch_opts* o, size_t* off_stage, size_t* off_final, size_t* off_run, size_t* per_launch,
+// Workspace layout for the options. A run holds at most max_steps x stage
+// launches per step x (cache groups) launch records of 4 n + 2 ints, n the
+// members of the group; summed over the groups of one stage that is at most
+// 6 max_instances ints.
+void layout(const sn_batch_opts* o, size_t* off_stage, size_t* off_final, size_t* off_run, size_t* run_ints,
             size_t* total) {
     const size_t n = (size_t)o->max_instances;
     const int lps = o->stepper == SN_HEUN ? 2 : 1;
@@ -82,10 +89,8 @@ void layout(const sn_batch_opts* o, size_t* off_stage, size_t* off_final, size_t
     *off_final = off;
     off += align256(n * sizeof(FinalizeArgs));
     *off_run = off;
-    // per stage launch: stage sel [n] (2 slot + variant), stage first [n + 1],
-    // finalize first [n + 1], finalize sel [n] (slot)
-    *per_launch = 4 * n + 2;
-    off += align256((size_t)o->max_steps_per_run * lps * (*per_launch) * sizeof(int32_t));
+    *run_ints = (size_t)o->max_steps_per_run * lps * (6 * n + 2);
+    off += align256(*run_ints * sizeof(int32_t));
     *total = off;
 }
 
@@ -129,6 +134,7 @@ sn_status sn_batch_create(const sn_batch_opts* opts, void* workspace, sn_batch**
     if (!B) return fail(SN_ERR_OOM, "batch allocation failed");
     try {
         B->slot.assign(opts->max_instances, nullptr);
+        B->quota.assign(opts->max_instances, 0);
     } catch (const std::bad_alloc&) {
         delete B;
         return fail(SN_ERR_OOM, "batch allocation failed");
@@ -140,8 +146,8 @@ sn_status sn_batch_create(const sn_batch_opts* opts, void* workspace, sn_batch**
     B->cus = std::max(cus, 1);
     B->launches_per_step = opts->stepper == SN_HEUN ? 2 : 1;
     size_t total;
-    layout(opts, &B->off_stage, &B->off_final, &B->off_run, &B->run_launch_ints, &total);
-    const size_t run_bytes = (size_t)opts->max_steps_per_run * B->launches_per_step * B->run_launch_ints * sizeof(int32_t);
+    layout(opts, &B->off_stage, &B->off_final, &B->off_run, &B->run_ints, &total);
+    const size_t run_bytes = B->run_ints * sizeof(int32_t);
     for (int h = 0; h < 2; ++h) {
         hipError_t e = hipHostMalloc((void**)&B->pinned[h], run_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&B->pinned_done[h], hipEventDisableTiming);
@@ -212,80 +218,109 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int n_slots = (int)B->slot.size();
     const int lps = B->launches_per_step;
-    const size_t per = B->run_launch_ints;
 
-    // Plan the run: for every step and stage, the unfinished plans in slot order.
+    // Plan the run. The unfinished plans form cache groups: plans whose two
+    // psi buffers fit the cache-group size are packed (slot order) into groups
+    // of at most that many bytes, so that a group's K steps run back to back
+    // out of the 256 MB Infinity Cache; larger plans, which stream from HBM
+    // anyway, form one group whose launches fill the GPU together. Each group
+    // takes its steps in turn; within a group every stage of every member is
+    // one launch (plus one finalize), members dropping out as they finish.
     std::vector<int64_t> left(n_slots, 0);
-    int steps = 0;
     int max_rects = 0;
-    for (int i = 0; i < n_slots; ++i) {
-        if (!B->slot[i]) continue;
-        left[i] = std::max<int64_t>(0, B->slot[i]->nt - B->slot[i]->step);
-        if (left[i] > 0) max_rects = std::max(max_rects, B->slot[i]->n_rects);
-        steps = (int)std::max<int64_t>(steps, std::min<int64_t>(left[i], n_steps));
+    std::vector<std::vector<int>> groups;
+    {
+        std::vector<int> big;
+        std::vector<int> cur;
+        uint64_t cur_bytes = 0;
+        const uint64_t cap = B->o.cache_group_bytes ? B->o.cache_group_bytes : (uint64_t)64 << 20;
+        for (int i = 0; i < n_slots; ++i) {
+            if (!B->slot[i]) continue;
+            left[i] = std::max<int64_t>(0, B->slot[i]->nt - B->slot[i]->step);
+            left[i] = std::min<int64_t>(left[i], n_steps);
+            if (B->quota[i] > 0) left[i] = std::min<int64_t>(left[i], B->quota[i]);
+            if (left[i] == 0) continue;
+            max_rects = std::max(max_rects, B->slot[i]->n_rects);
+            const uint64_t f = 2 * (uint64_t)B->slot[i]->psi_bytes;
+            if (f > cap) {
+                big.push_back(i);
+                continue;
+            }
+            if (!cur.empty() && cur_bytes + f > cap) {
+                groups.push_back(cur);
+                cur.clear();
+                cur_bytes = 0;
+            }
+            cur.push_back(i);
+            cur_bytes += f;
+        }
+        if (!cur.empty()) groups.push_back(cur);
+        if (!big.empty()) groups.push_back(big);
     }
-    if (steps == 0) return SN_OK;
+    if (groups.empty()) return SN_OK;
+    struct Rec {
+        size_t off;  // ints into the run area: sel [n], first [n+1], ffirst [n+1], fsel [n]
+        int32_t n, total, ftotal, mode;
+    };
+    std::vector<Rec> recs;
     std::vector<int32_t> host;
-    std::vector<int32_t> totals;  // per launch: stage total, finalize total, n_sel
+    int64_t stage_launches = 0;
     try {
-        host.assign((size_t)steps * lps * per, 0);
-        totals.assign((size_t)steps * lps * 3, 0);
+        for (const auto& g : groups) {
+            int64_t steps = 0;
+            for (int i : g) steps = std::max(steps, left[i]);
+            for (int t = 0; t < steps; ++t) {
+                for (int st = 0; st < lps; ++st) {
+                    Rec r{host.size(), 0, 0, 0, (B->o.stepper == SN_HEUN && st == 1) ? (int32_t)kAverage : (int32_t)kUpdate};
+                    std::vector<int32_t> sel, first, ffirst, fsel;
+                    for (int i : g) {
+                        if (left[i] <= t) continue;
+                        const sn_plan* P = B->slot[i];
+                        const int variant = P->stepper == SN_EULER ? ((P->cur + t) & 1) : st;
+                        sel.push_back(2 * i + variant);
+                        fsel.push_back(i);
+                        first.push_back(r.total);
+                        ffirst.push_back(r.ftotal);
+                        r.total += P->n_wg;
+                        r.ftotal += P->nq + (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
+                    }
+                    r.n = (int32_t)sel.size();
+                    first.push_back(r.total);
+                    ffirst.push_back(r.ftotal);
+                    host.insert(host.end(), sel.begin(), sel.end());
+                    host.insert(host.end(), first.begin(), first.end());
+                    host.insert(host.end(), ffirst.begin(), ffirst.end());
+                    host.insert(host.end(), fsel.begin(), fsel.end());
+                    recs.push_back(r);
+                    ++stage_launches;
+                }
+            }
+        }
     } catch (const std::bad_alloc&) {
         return fail(SN_ERR_OOM, "host run tables");
     }
-    for (int t = 0; t < steps; ++t) {
-        for (int st = 0; st < lps; ++st) {
-            const size_t L = (size_t)t * lps + st;
-            int32_t* sel = host.data() + L * per;
-            int32_t* first = sel + B->o.max_instances;
-            int32_t* ffirst = first + B->o.max_instances + 1;
-            int32_t* fsel = ffirst + B->o.max_instances + 1;
-            int n = 0, tot = 0, ftot = 0;
-            for (int i = 0; i < n_slots; ++i) {
-                if (!B->slot[i] || left[i] <= t) continue;
-                const sn_plan* P = B->slot[i];
-                int variant = st;
-                if (P->stepper == SN_EULER) variant = (P->cur + t) & 1;
-                sel[n] = 2 * i + variant;
-                fsel[n] = i;
-                first[n] = tot;
-                ffirst[n] = ftot;
-                tot += P->n_wg;
-                ftot += P->nq + (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
-                ++n;
-            }
-            first[n] = tot;
-            ffirst[n] = ftot;
-            totals[L * 3 + 0] = tot;
-            totals[L * 3 + 1] = ftot;
-            totals[L * 3 + 2] = n;
-        }
-    }
+    if (host.size() > B->run_ints) return fail(SN_ERR_INVALID, "run tables exceed the workspace (internal)");
 
     auto issue = [&](hipStream_t q) -> sn_status {
-        for (int t = 0; t < steps; ++t) {
-            for (int st = 0; st < lps; ++st) {
-                const size_t L = (size_t)t * lps + st;
-                const int32_t* dsel = reinterpret_cast<const int32_t*>(B->ws + B->off_run) + L * per;
-                BatchLaunch bl{};
-                bl.args = reinterpret_cast<const StageArgs*>(B->ws + B->off_stage);
-                bl.sel = dsel;
-                bl.first = dsel + B->o.max_instances;
-                bl.n_sel = totals[L * 3 + 2];
-                bl.total = totals[L * 3 + 0];
-                const int mode = (B->o.stepper == SN_HEUN && st == 1) ? kAverage : kUpdate;
-                const int per_cu = B->o.waves_per_group == 4 ? 8 : (B->o.waves_per_group == 8 ? 4 : 2);
-                HIP_TRY(launch_stage_batch(B->o.order, mode, B->o.psi_dtype, B->o.rows_per_wave, B->o.waves_per_group,
-                                           bl, grid_for(B, bl.total, per_cu), max_rects, q),
-                        "batched stage launch");
-                FinalizeBatch fb{};
-                fb.args = reinterpret_cast<const FinalizeArgs*>(B->ws + B->off_final);
-                fb.first = dsel + 2 * B->o.max_instances + 1;
-                fb.sel = dsel + 3 * B->o.max_instances + 2;
-                fb.n_sel = totals[L * 3 + 2];
-                fb.total = totals[L * 3 + 1];
-                HIP_TRY(launch_finalize_batch(fb, grid_for(B, fb.total, 8), q), "batched finalize launch");
-            }
+        const int32_t* base = reinterpret_cast<const int32_t*>(B->ws + B->off_run);
+        for (const Rec& r : recs) {
+            const int32_t* d = base + r.off;
+            BatchLaunch bl{};
+            bl.args = reinterpret_cast<const StageArgs*>(B->ws + B->off_stage);
+            bl.sel = d;
+            bl.first = d + r.n;
+            bl.n_sel = r.n;
+            bl.total = r.total;
+            HIP_TRY(launch_stage_batch(B->o.order, r.mode, B->o.psi_dtype, B->o.rows_per_wave, B->o.waves_per_group,
+                                       bl, B->o.workgroups_per_cu, B->cus, max_rects, q),
+                    "batched stage launch");
+            FinalizeBatch fb{};
+            fb.args = reinterpret_cast<const FinalizeArgs*>(B->ws + B->off_final);
+            fb.first = d + 2 * r.n + 1;
+            fb.sel = d + 3 * r.n + 2;
+            fb.n_sel = r.n;
+            fb.total = r.ftotal;
+            HIP_TRY(launch_finalize_batch(fb, grid_for(B, fb.total, 8), q), "batched finalize launch");
         }
         return SN_OK;
     };
@@ -294,10 +329,16 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     // only; an identical run under an unchanged admitted set replays the graph.
     std::vector<int32_t> key;
     if (B->o.use_graph) {
-        key.reserve(host.size() + totals.size() + 2);
-        key.push_back(steps);
+        key.reserve(host.size() + 5 * recs.size() + 2);
+        key.push_back((int32_t)recs.size());
         key.push_back(max_rects);
-        key.insert(key.end(), totals.begin(), totals.end());
+        for (const Rec& r : recs) {
+            key.push_back((int32_t)r.off);
+            key.push_back(r.n);
+            key.push_back(r.total);
+            key.push_back(r.ftotal);
+            key.push_back(r.mode);
+        }
         key.insert(key.end(), host.begin(), host.end());
     }
     const bool replay = B->o.use_graph && B->graph_exec && B->graph_epoch == B->epoch && key == B->graph_key;
@@ -340,14 +381,22 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             if (st != SN_OK) return st;
         }
     }
-    B->launches += (int64_t)steps * lps;
+    B->launches += stage_launches;
     for (int i = 0; i < n_slots; ++i) {
         sn_plan* P = B->slot[i];
         if (!P) continue;
-        const int64_t k = std::min<int64_t>(left[i], steps);
-        P->step += k;
-        if (P->stepper == SN_EULER) P->cur ^= (int)(k & 1);
+        P->step += left[i];
+        if (P->stepper == SN_EULER) P->cur ^= (int)(left[i] & 1);
     }
+    return SN_OK;
+}
+
+sn_status sn_batch_set_steps(sn_batch* B, int32_t slot, int32_t steps) {
+    if (!B) return fail(SN_ERR_INVALID, "batch is NULL");
+    if (slot < 0 || slot >= (int)B->slot.size() || !B->slot[slot]) return fail(SN_ERR_INVALID, "slot %d is not admitted", slot);
+    if (steps < 0 || steps > B->o.max_steps_per_run)
+        return fail(SN_ERR_INVALID, "steps = %d out of range [0, %d]", steps, B->o.max_steps_per_run);
+    B->quota[slot] = steps;
     return SN_OK;
 }
 
@@ -367,6 +416,7 @@ sn_status sn_batch_retire(sn_batch* B, int32_t slot) {
     B->bytes_admitted -= footprint(P);
     P->batch = nullptr;
     B->slot[slot] = nullptr;
+    B->quota[slot] = 0;
     B->epoch++;
     return SN_OK;
 }

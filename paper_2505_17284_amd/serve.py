@@ -1,0 +1,282 @@
+"""Request loops over the batched S_N solver: continuous batching vs one solve at a time.
+
+Continuous batching (``serve``): requests arrive on a wall clock (Poisson
+arrivals from ``inputs.serving_requests``); a request is admitted as soon as a
+slot of the batch for its storage type and the shared HBM budget allow, its
+state stays on the device, and every window of K steps advances all admitted
+unfinished requests together (one persistent launch per stage, replayed from a
+captured hipGraph while the set is unchanged). Finished requests return their
+QoIs to the host and free their slot and memory at once.
+
+The plain path (``serve_fifo``) solves one request at a time in arrival order
+with the single-plan API.
+
+Latency = time from a request's arrival to its QoIs on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import batch as B
+from . import inputs as I
+from . import solver
+
+
+def _sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else float("nan")
+
+
+def step_cost(p) -> float:
+    """Bytes one step of a problem moves (cells x ordinates x bytes per stored psi)."""
+    return float(p.cell_ordinates) * (2.0 if p.psi_dtype == "bf16" else 4.0)
+
+
+def work_quotas(costs: dict, k: int) -> dict:
+    """Steps per run so that every admitted problem gets about the same GPU
+    time per run: the cheapest takes k steps, a problem c times as expensive
+    k / c (at least 1)."""
+    if not costs:
+        return {}
+    cmin = min(costs.values())
+    return {key: max(1, min(k, int(round(k * cmin / c)))) for key, c in costs.items()}
+
+
+def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_run: int = 32,
+          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "work", verbose: bool = False):
+    """Continuous batching over `requests` = [(arrival_s, Problem)], Heun + minmod.
+
+    policy "work": per-run step quotas share the GPU by work (short requests
+    are not held to the pace of long ones); "steps": every admitted request
+    takes steps_per_run steps per run. Returns per-request records and totals."""
+    dtypes = sorted({p.psi_dtype for _, p in requests})
+    batches = {d: B.Batch(order=2, stepper=I.HEUN, psi_dtype=d, max_instances=max_instances,
+                          steps_per_run=steps_per_run, rows_per_wave=rows_per_wave,
+                          waves_per_group=waves_per_group) for d in dtypes}
+    fps = [B.footprint(p, rows_per_wave, waves_per_group) for _, p in requests]
+    for i, f in enumerate(fps):
+        if f > hbm_budget_bytes:
+            raise ValueError(f"request {i} needs {f} bytes, more than the whole budget")
+    used = 0
+    peak = 0
+    queue: list[int] = []
+    slot_of: dict[tuple, int] = {}
+    rec = [dict(arrival=a, name=p.name, n=p.nx, M=p.M, dtype=p.psi_dtype, cell_ord_steps=0,
+                admitted=None, done=None) for a, p in requests]
+    nxt = 0
+    finished = 0
+    changed = False
+    t0 = time.perf_counter()
+    windows = 0
+    try:
+        while finished < len(requests):
+            now = time.perf_counter() - t0
+            while nxt < len(requests) and requests[nxt][0] <= now:
+                queue.append(nxt)
+                nxt += 1
+            # FIFO admission, no overtaking: the head waits for budget or a slot
+            while queue:
+                i = queue[0]
+                p = requests[i][1]
+                b = batches[p.psi_dtype]
+                if used + fps[i] > hbm_budget_bytes or len(b.plans) >= max_instances:
+                    break
+                queue.pop(0)
+                s = b.admit(p)
+                slot_of[(p.psi_dtype, s)] = i
+                used += fps[i]
+                peak = max(peak, used)
+                rec[i]["admitted"] = time.perf_counter() - t0
+                changed = True
+            if policy == "work" and changed:
+                costs = {key: step_cost(requests[i][1]) for key, i in slot_of.items()}
+                for (d, s), q in work_quotas(costs, steps_per_run).items():
+                    batches[d].set_steps(s, q)
+                changed = False
+            active = [b for b in batches.values() if b.unfinished()]
+            if not active:
+                if nxt < len(requests):
+                    time.sleep(max(0.0, requests[nxt][0] - (time.perf_counter() - t0)))
+                continue
+            for b in active:
+                b.run()
+            windows += 1
+            _sync()
+            for d, b in batches.items():
+                for s in b.done_slots():
+                    i = slot_of.pop((d, s))
+                    r = b.result(s, allow_nonfinite=True)
+                    rec[i]["done"] = time.perf_counter() - t0
+                    rec[i]["nonfinite"] = r["nonfinite"]
+                    rec[i]["latency"] = rec[i]["done"] - rec[i]["arrival"]
+                    rec[i]["nt"] = r["nt"]
+                    rec[i]["qoi_int"] = r["qoi_int"]
+                    rec[i]["cell_ord_steps"] = requests[i][1].cell_ordinates * r["nt"]
+                    b.retire(s)
+                    used -= fps[i]
+                    finished += 1
+                    changed = True
+                    if verbose:
+                        print(f"[serve] {rec[i]['name']} latency {rec[i]['latency']:.3f} s", file=sys.stderr,
+                              flush=True)
+    finally:
+        for b in batches.values():
+            b.close()
+    wall = time.perf_counter() - t0
+    return rec, dict(wall_s=wall, windows=windows, peak_bytes=peak)
+
+
+def serve_fifo(requests, verbose: bool = False, rows_per_wave: int = 2, waves_per_group: int = 4):
+    """One request at a time, in arrival order, through the single-plan path."""
+    rec = []
+    t0 = time.perf_counter()
+    for a, p in requests:
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+        start = time.perf_counter() - t0
+        plan = solver.Plan(p, rows_per_wave=rows_per_wave, waves_per_group=waves_per_group)
+        try:
+            plan.run()
+            r = plan.qoi(allow_nonfinite=True)
+            r["nt"] = plan.n_steps
+        finally:
+            plan.close()
+        done = time.perf_counter() - t0
+        rec.append(dict(arrival=a, name=p.name, n=p.nx, M=p.M, dtype=p.psi_dtype, start=start, done=done,
+                        latency=done - a, service=done - start, nt=r["nt"], qoi_int=r["qoi_int"],
+                        nonfinite=r["nonfinite"],
+                        cell_ord_steps=p.cell_ordinates * r["nt"]))
+        if verbose:
+            print(f"[fifo] {p.name} service {done - start:.3f} s latency {done - a:.3f} s", file=sys.stderr,
+                  flush=True)
+    return rec, dict(wall_s=time.perf_counter() - t0)
+
+
+def summarize(rec, totals, alone_service=None):
+    lat = [r["latency"] for r in rec]
+    first = min(r["arrival"] for r in rec)
+    last = max(r["done"] for r in rec)
+    out = dict(requests=len(rec), nonfinite=sum(1 for r in rec if r.get("nonfinite")), p50_latency_s=percentile(lat, 50), p99_latency_s=percentile(lat, 99),
+               mean_latency_s=float(np.mean(lat)), solves_per_s=len(rec) / max(last - first, 1e-9),
+               updates_per_s=sum(r["cell_ord_steps"] for r in rec) / max(last - first, 1e-9), **totals)
+    if alone_service is not None:
+        slow = [r["latency"] / max(alone_service[r["name"]], 1e-9) for r in rec]
+        out["p99_slowdown"] = percentile(slow, 99)
+        out["p50_slowdown"] = percentile(slow, 50)
+    return out
+
+
+def same_results(rec_a, rec_b, rtol: float = 1e-5):
+    """Largest relative difference of any integrated QoI between two runs of the same requests."""
+    worst = 0.0
+    for a, b in zip(rec_a, rec_b):
+        assert a["name"] == b["name"]
+        for k, va in a["qoi_int"].items():
+            vb = b["qoi_int"][k]
+            scale = max(abs(va), abs(vb), 1e-300)
+            worst = max(worst, abs(va - vb) / scale)
+    return worst
+
+
+def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_alone: bool = True,
+       psi_dtype: str = "f32", verbose: bool = False):
+    """The batched UQ workload: DP-2 lattice draws, all admitted at once, run to T."""
+    probs = [I.uq_instance(seed0 + s, psi_dtype=psi_dtype) for s in range(n_instances)]
+    work = 0
+    for p in probs:
+        nt = solver.plan_info(p)["n_steps"]
+        work += p.cell_ordinates * nt
+    _sync()
+    t0 = time.perf_counter()
+    b = B.Batch(order=2, stepper=I.HEUN, psi_dtype=psi_dtype, max_instances=n_instances,
+                steps_per_run=steps_per_run)
+    try:
+        slots = [b.admit(p) for p in probs]
+        t_admit = time.perf_counter() - t0
+        while b.unfinished():
+            b.run()
+        res = [b.result(s) for s in slots]
+        _sync()
+        secs = time.perf_counter() - t0
+        info = b.info()
+        peak = info["bytes_admitted"]
+    finally:
+        b.close()
+    out = dict(instances=n_instances, wall_s=secs, admit_s=t_admit, solves_per_s=n_instances / secs,
+               updates_per_s=work / secs, cell_ord_steps=work, peak_bytes=peak,
+               graph_replays=info["graph_replays"], launches=info["launches"])
+    if compare_alone:
+        _sync()
+        t0 = time.perf_counter()
+        alone = [solver.solve(p) for p in probs]
+        _sync()
+        secs_a = time.perf_counter() - t0
+        out["alone_wall_s"] = secs_a
+        out["alone_solves_per_s"] = n_instances / secs_a
+        out["speedup_vs_alone"] = secs_a / secs
+        out["max_rel_diff_vs_alone"] = same_results(
+            [dict(name=p.name, qoi_int=r["qoi_int"]) for p, r in zip(probs, res)],
+            [dict(name=p.name, qoi_int=r["qoi_int"]) for p, r in zip(probs, alone)])
+    if verbose:
+        print(f"[uq] {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def sweep(n_requests: int = 24, rates=(0.5, 0.9), seed: int = 0, budget_gb: float = 200.0,
+          dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32, policy: str = "work",
+          verbose: bool = False):
+    """Capacity from the one-at-a-time path, then both paths at fractions of it."""
+    base = I.serving_requests(n_requests, rate=1.0, seed=seed, dtypes=dtypes)
+    # capacity: back-to-back service times of the plain path (arrivals all at 0)
+    cap_reqs = [(0.0, p) for _, p in base]
+    cap_rec, _ = serve_fifo(cap_reqs, verbose=verbose)
+    alone = {r["name"]: r["service"] for r in cap_rec}
+    capacity = len(cap_rec) / sum(alone.values())
+    out = dict(capacity_solves_per_s=capacity, mean_service_s=float(np.mean(list(alone.values()))),
+               policy=policy, steps_per_run=steps_per_run, rates=[])
+    for f in rates:
+        lam = f * capacity
+        # same requests, arrival times rescaled to rate lam
+        arr = [(t / lam, p) for t, p in base]
+        rec_b, tot_b = serve(arr, int(budget_gb * 1e9), max_instances=max_instances, steps_per_run=steps_per_run,
+                             policy=policy, verbose=verbose)
+        rec_f, tot_f = serve_fifo(arr, verbose=verbose)
+        out["rates"].append(dict(load=f, rate_per_s=lam,
+                                 batched=summarize(rec_b, tot_b, alone),
+                                 fifo=summarize(rec_f, tot_f, alone),
+                                 max_rel_diff_batched_vs_fifo=same_results(rec_b, rec_f)))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.1")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--uq", type=int, default=0, help="run the UQ batch with this many instances")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args(argv)
+    res = {}
+    if args.uq:
+        res["uq"] = uq(args.uq, verbose=args.verbose)
+    if args.requests:
+        res["serving"] = sweep(args.requests, tuple(float(x) for x in args.rates.split(",")), args.seed,
+                               args.budget_gb, verbose=args.verbose)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
