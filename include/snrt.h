@@ -159,7 +159,8 @@ sn_status sn_plan_create(const sn_problem *problem, sn_plan **out);
 
 /* Same, with an explicit launch shape (0 = library default for each):
  * group_size ordinates per workgroup, rows_per_wave grid rows per wavefront
- * (2 or 4), waves_per_group wavefronts per workgroup (4, 8 or 16). Returns
+ * (2 or 4), waves_per_group compute wavefronts per workgroup (4 or 8; one
+ * more wavefront stages rows for them). Returns
  * SN_ERR_UNSUPPORTED for a shape the library was not compiled for. */
 sn_status sn_plan_create_tuned(const sn_problem *problem, int32_t group_size,
                                int32_t rows_per_wave, int32_t waves_per_group,

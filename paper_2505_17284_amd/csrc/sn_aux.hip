@@ -40,26 +40,26 @@ __device__ __forceinline__ void ghost_update(const GhostArgs& a, int k, int idx)
     const T* pmx = psi + (int64_t)o.mx * a.plane;
     const T* pmy = psi + (int64_t)o.my * a.plane;
     const int64_t P = a.pitch;
-    const int nx = a.nx, ny = a.ny;
+    const int nx = a.nx, ny = a.ny, ox = a.ox;
     if (idx < ny) {
         const int64_t row = (int64_t)(idx + kGhost) * P;
         if (sx) {  // enters through W
-            const float g = a.bc[kW] == kReflect ? ld(pmx + row + kGhost) : a.ghost[kW];
-            st(pk + row + 1, g);
-            st(pk + row + 0, g);
+            const float g = a.bc[kW] == kReflect ? ld(pmx + row + ox) : a.ghost[kW];
+            st(pk + row + ox - 1, g);
+            st(pk + row + ox - 2, g);
         } else {
-            st(pk + row + 1, ld(pk + row + kGhost));
+            st(pk + row + ox - 1, ld(pk + row + ox));
         }
         if (!sx) {  // enters through E
-            const float g = a.bc[kE] == kReflect ? ld(pmx + row + kGhost + nx - 1) : a.ghost[kE];
-            st(pk + row + kGhost + nx, g);
-            st(pk + row + kGhost + nx + 1, g);
+            const float g = a.bc[kE] == kReflect ? ld(pmx + row + ox + nx - 1) : a.ghost[kE];
+            st(pk + row + ox + nx, g);
+            st(pk + row + ox + nx + 1, g);
         } else {
-            st(pk + row + kGhost + nx, ld(pk + row + kGhost + nx - 1));
+            st(pk + row + ox + nx, ld(pk + row + ox + nx - 1));
         }
     }
     if (idx < nx) {
-        const int64_t col = idx + kGhost;
+        const int64_t col = idx + ox;
         if (sy) {  // enters through S
             const float g = a.bc[kS] == kReflect ? ld(pmy + kGhost * P + col) : a.ghost[kS];
             st(pk + 1 * P + col, g);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
             acc.z += p.z;
             acc.w += p.w;
         }
-        const int i0 = 4 * c4 - kGhost;  // interior column of the first of the four
+        const int i0 = 4 * c4 - a.ox;  // interior column of the first of the four
         if (i0 >= 0 && i0 + 3 < a.nx) {
             *reinterpret_cast<float4*>(a.phi + off) = acc;
         } else {
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(256) sn_phi_init_kernel(const PhiInitArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (int64_t)a.nx * a.ny) return;
     const int64_t j = c / a.nx, i = c - j * a.nx;
-    const int64_t off = (j + kGhost) * a.pitch + i + kGhost;
+    const int64_t off = (j + kGhost) * a.pitch + i + a.ox;
     const T* psi = static_cast<const T*>(a.psi);
     float acc = 0.0f;
     for (int k = 0; k < a.M; ++k) acc = fmaf(a.ord[k].w, ld(psi + (int64_t)k * a.plane + off), acc);
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) sn_phi_init_kernel(const PhiInitArgs a) {
 
 // ---------------------------------------------------------------- launchers
 bool supported_shape(int rows, int waves) {
-    return (rows == 2 || rows == 4) && (waves == 4 || waves == 8 || waves == 16);
+    return (rows == 2 || rows == 4) && (waves == 4 || waves == 8);
 }
 
 hipError_t launch_stage(int order, int mode, int dtype, int rows, int waves, const StageArgs& a, hipStream_t s) {

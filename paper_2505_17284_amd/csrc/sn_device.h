@@ -3,13 +3,17 @@
 // Internal to libsnrt; not part of the C ABI.
 //
 // Device layout of every per-cell plane (psi per ordinate, phi, its
-// per-group partials, the region map): [ny_alloc][pitch] elements with a
-// frame of two ghost cells on every side. Interior cell (i, j) sits at
-//     origin + j * pitch + i,    origin = 2 * pitch + 2.
-// The ghost cells of psi carry, per ordinate and side, the value that makes
-// the interior reconstruction formula produce the boundary traces of the
-// method (see sn_stage_impl.h); the stage kernels write them for the state
-// they produce.
+// per-group partials, the region map): [ny_alloc][pitch] elements, rows of a
+// whole number of 128-byte lines of psi. Interior cell (i, j) sits at
+//     origin + j * pitch + i,    origin = 2 * pitch + ox,
+// ox = 128 / sizeof(psi element) (32 for FP32, 64 for BF16), so that every
+// 128-column tile of a row starts on a 128-byte line and the stage kernels
+// write whole lines. Around the interior is a frame of two ghost cells on
+// every side (columns ox - 2, ox - 1, ox + nx, ox + nx + 1; rows 0, 1,
+// ny + 2, ny + 3). The ghost cells of psi carry, per ordinate and side, the
+// value that makes the interior reconstruction formula produce the boundary
+// traces of the method (see sn_stage_impl.h); the stage kernels write them for
+// the state they produce.
 #pragma once
 
 #include <stdint.h>
@@ -20,7 +24,7 @@ namespace snk {
 
 constexpr int kWave = 64;                      // CDNA wavefront width
 constexpr int kCellsPerLane = 2;               // consecutive x-cells held by one lane
-constexpr int kTileX = kCellsPerLane * (kWave - 2);  // 124 output columns per wave (lanes 1..62)
+constexpr int kTileX = kCellsPerLane * kWave;  // 128 output columns per wave (two per lane)
 constexpr int kGhost = 2;                      // ghost-frame width
 constexpr int kMaxTallies = 8;
 constexpr int kMaxRects = 4;
@@ -70,6 +74,7 @@ struct StageArgs {
     double* qpart;          // [nq][n_wg] per-workgroup QoI partial sums
     int64_t plane;          // ny_alloc * pitch (elements)
     int32_t nx, ny, pitch, M;
+    int32_t ox;             // column of interior cell 0 in a row
     int32_t G, Mg;          // ordinate groups and ordinates per group
     int32_t ntx, nty;       // tiles along x (124 columns) and y (waves * rows_per_wave rows)
     int32_t n_wg;
@@ -103,7 +108,7 @@ struct GhostArgs {
     void* psi;
     const OrdConst* ord;
     int64_t plane;
-    int32_t nx, ny, pitch, M;
+    int32_t nx, ny, pitch, M, ox;
     int32_t bc[4];
     float ghost[4];  // inflow value per side (0 for vacuum)
 };
@@ -112,7 +117,7 @@ struct FinalizeArgs {
     const float* phi_part;  // [G] planes written by the stage
     float* phi;             // their sum: phi of the stage output
     int64_t plane;
-    int32_t nx, ny, pitch, G;
+    int32_t nx, ny, pitch, G, ox;
     int32_t n_phi_wg;       // workgroups reducing phi (0: the stage wrote no partials)
     const double* qpart;    // [nq][n_wg]
     const double* scale;    // [nq]
@@ -128,7 +133,7 @@ struct PhiInitArgs {
     float* phi;
     const OrdConst* ord;
     int64_t plane;
-    int32_t nx, ny, pitch, M;
+    int32_t nx, ny, pitch, M, ox;
 };
 
 // Launchers. dtype: 0 = f32, 1 = bf16.

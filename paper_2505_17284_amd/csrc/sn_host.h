@@ -51,7 +51,7 @@ struct sn_plan {
     // derived
     int nt = 0;
     double dt = 0;
-    int pitch = 0, ny_alloc = 0;
+    int pitch = 0, ny_alloc = 0, ox = 2;
     int64_t plane = 0, origin = 0;
     int G = 1, Mg = 1, rows = 2, waves = 4;
     int ntx = 0, nty = 0, n_wg = 0, nq = 0;

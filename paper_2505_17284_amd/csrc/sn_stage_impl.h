@@ -126,16 +126,19 @@ struct Store<uint16_t> {
 };
 
 // ---------------------------------------------------------------- helpers
-// Lane l receives x from lane l-1 (lane 0 reads 0): DPP wave_shr:1. Lanes 0
-// and 63 are halo lanes whose results are never stored, so the value shifted
-// in at the wave's edge does not matter; bound_ctrl lets the move fold into
-// the instruction that consumes it.
-__device__ __forceinline__ float lane_from_left(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138, 0xf, 0xf, true));
+// Lane l receives x from lane l-1; lane 0, which has no source lane, keeps
+// `edge` (DPP wave_shr:1 with bound_ctrl off). One instruction over the full
+// wave: writing this as a select on the lane index lets the compiler mask
+// lane 0 out of EXEC around the move, and a masked-out lane is no valid
+// source for lane 1.
+__device__ __forceinline__ float lane_from_left(float x, float edge) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(x), 0x138, 0xf, 0xf, false));
 }
-// Lane l receives x from lane l+1 (lane 63 reads 0): DPP wave_shl:1.
-__device__ __forceinline__ float lane_from_right(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130, 0xf, 0xf, true));
+// Lane l receives x from lane l+1; lane 63 keeps `edge` (DPP wave_shl:1).
+__device__ __forceinline__ float lane_from_right(float x, float edge) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(x), 0x130, 0xf, 0xf, false));
 }
 
 // minmod(a, b): the argument of smaller magnitude when both have the same
@@ -212,43 +215,128 @@ struct WaveCtx {
     uint32_t tags[TY];   // face tags, cell 0 in the low half
 };
 
-// Rows of one ordinate staged in LDS for the whole workgroup: the 4 waves
-// share their halo rows, so a workgroup reads 4 TY + 4 rows per ordinate
-// instead of 4 (TY + 4). Thread (wave, lane) loads staged rows wave + 4 m.
-template <int TY, int W>
-struct RowStage {
-    static constexpr int kRows = W * TY + 4;             // staged rows per ordinate
-    static constexpr int kPer = (kRows + W - 1) / W;     // rows loaded per thread
+// ---------------------------------------------------------------- row staging
+// A workgroup is W compute waves stacked in y plus one loader wave. For every
+// ordinate the loader copies the workgroup's W TY + 4 stencil rows (and, for
+// the averaging stage, the W TY rows of psi^n) from HBM straight into a ring
+// of kSlots LDS slots (buffer loads with an LDS destination), two ordinates
+// ahead of the compute waves; one barrier per ordinate hands a slot over. The
+// compute waves issue no global loads in the ordinate loop and the loader no
+// stores, so neither waits on the other's memory traffic (the wait counters
+// are per wave).
+#ifndef SN_RING_SLOTS
+#define SN_RING_SLOTS 3
+#endif
+
+template <typename T, int TY, int W, int MODE>
+struct Ring {
+    static constexpr int kSlots = SN_RING_SLOTS;  // ordinates in flight + the one being computed
+    static_assert(kSlots >= 2 && kSlots <= 5, "ring depth");
+    static constexpr int kRows = W * TY + 4;                             // stencil rows
+    static constexpr int kOldRows = MODE == kAverage ? W * TY : 0;       // psi^n rows
+    static constexpr int kRowBytes = kWave * 2 * (int)sizeof(T);         // 128 cells
+    static constexpr int kDmaBytes = sizeof(T) == 4 ? 16 : 4;            // bytes per lane per copy
+    static constexpr int kRowsPerDma = kWave * kDmaBytes / kRowBytes;    // 2 (f32) or 1 (bf16)
+    static constexpr int kLanesPerRow = kWave / kRowsPerDma;
+    static constexpr int kDmaStencil = (kRows + kRowsPerDma - 1) / kRowsPerDma;
+    static constexpr int kDmaOld = (kOldRows + kRowsPerDma - 1) / kRowsPerDma;
+    static constexpr int kOldRow0 = kDmaStencil * kRowsPerDma;           // first psi^n row of a slot
+    static constexpr int kSlotRows = kOldRow0 + kDmaOld * kRowsPerDma;
+    // x-halo of the output rows: cells -2, -1, 128, 129 of the tile, one
+    // dword per lane (4 lanes per row for FP32, 2 for BF16)
+    static constexpr int kHaloRowBytes = 4 * (int)sizeof(T);
+    static constexpr int kHaloLanesPerRow = kHaloRowBytes / 4;
+    static constexpr int kHaloRowsPerDma = kWave / kHaloLanesPerRow;
+    static constexpr int kDmaHalo = (W * TY + kHaloRowsPerDma - 1) / kHaloRowsPerDma;
+    static constexpr int kHaloOffset = kSlotRows * kRowBytes;             // bytes into the slot
+    static constexpr int kSlotBytes = kHaloOffset + kDmaHalo * kWave * 4;
+    static constexpr int kDmaPerOrd = kDmaStencil + kDmaOld + kDmaHalo;  // copies per ordinate
+    static constexpr int kBytes = kSlots * kSlotBytes;
+    // outstanding copies allowed while waiting for the oldest ordinate when
+    // `ahead` later ordinates are in flight (the counter field holds at most
+    // 63: waiting for more is only conservative)
+    static constexpr int wait_ahead(int ahead) { return kDmaPerOrd * ahead < 64 ? kDmaPerOrd * ahead : 63; }
 };
 
-template <typename T, int TY, int W>
-__device__ __forceinline__ void stage_issue(SArgs a, int k, int yw, int wave, const WaveCtx<TY>& w,
-                                            float2 (&pre)[RowStage<TY, W>::kPer]) {
-    const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_in) + (size_t)k * w.planeb, w.planeb);
+using lds_ptr = __attribute__((address_space(3))) void*;
+
+// s_waitcnt with only the vector-memory count constrained (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at maximum).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Loader: ordinate k's rows into ring slot `slot`. Lane l copies kDmaBytes at
+// column offset (l % kLanesPerRow) kDmaBytes of row l / kLanesPerRow of each
+// kRowsPerDma-row block; the LDS copy lands at the block's base + l kDmaBytes,
+// i.e. row-major [row][128 cells], the layout the compute lanes read.
+template <typename T, int TY, int W, int MODE>
+__device__ __forceinline__ void ring_issue(SArgs a, int k, int yw, uint32_t tile_off, uint32_t pitchb,
+                                           uint32_t planeb, char* slot) {
+    using R = Ring<T, TY, W, MODE>;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t voff = tile_off + (uint32_t)(lane % R::kLanesPerRow) * R::kDmaBytes +
+                          (uint32_t)(lane / R::kLanesPerRow) * pitchb;
+    const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_in) + (size_t)k * planeb, planeb);
 #pragma unroll
-    for (int m = 0; m < RowStage<TY, W>::kPer; ++m) {
-        const int q = wave + W * m;
-        if (q < RowStage<TY, W>::kRows) pre[m] = Store<T>::bload2(r, w.lane_off, (uint32_t)(yw + q) * w.pitchb);
+    for (int i = 0; i < R::kDmaStencil; ++i)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(slot + i * R::kRowsPerDma * R::kRowBytes),
+                                                 R::kDmaBytes, voff, (uint32_t)(yw + i * R::kRowsPerDma) * pitchb,
+                                                 0, 0);
+    {
+        // x-halo: lane l covers dword (l % kHaloLanesPerRow) of output row l / kHaloLanesPerRow;
+        // the first half of a row's dwords sit left of the tile, the rest right
+        const int e = lane % R::kHaloLanesPerRow, hr = lane / R::kHaloLanesPerRow;
+        const int half = R::kHaloLanesPerRow / 2;
+        // rows past the workgroup's output rows are not needed: their copies
+        // carry the out-of-range offset and fetch nothing
+        const uint32_t hoff = hr >= W * TY ? kDropOffset
+                                           : (e < half ? tile_off - 2 * (uint32_t)sizeof(T) + 4 * e
+                                                       : tile_off + (uint32_t)(kTileX * sizeof(T)) + 4 * (e - half)) +
+                                                 (uint32_t)hr * pitchb;
+#pragma unroll
+        for (int i = 0; i < R::kDmaHalo; ++i)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(slot + R::kHaloOffset + i * kWave * 4), 4, hoff,
+                                                     (uint32_t)(yw + kGhost + i * R::kHaloRowsPerDma) * pitchb, 0, 0);
+    }
+    if (MODE == kAverage) {
+        const rsrc_t ro = make_rsrc(static_cast<const char*>(a.psi_old) + (size_t)k * planeb, planeb);
+#pragma unroll
+        for (int i = 0; i < R::kDmaOld; ++i)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                ro, (lds_ptr)(slot + (R::kOldRow0 + i * R::kRowsPerDma) * R::kRowBytes), R::kDmaBytes, voff,
+                (uint32_t)(yw + kGhost + i * R::kRowsPerDma) * pitchb, 0, 0);
     }
 }
 
-template <int TY, int W>
-__device__ __forceinline__ void stage_commit(float2 (*buf)[kWave], int wave, int lane,
-                                             const float2 (&pre)[RowStage<TY, W>::kPer]) {
-#pragma unroll
-    for (int m = 0; m < RowStage<TY, W>::kPer; ++m) {
-        const int q = wave + W * m;
-        if (q < RowStage<TY, W>::kRows) buf[q][lane] = pre[m];
-    }
+// One staged cell pair of the compute lane `lane` from LDS.
+template <typename T>
+__device__ __forceinline__ float2 ring_read(const char* row, int lane);
+template <>
+__device__ __forceinline__ float2 ring_read<float>(const char* row, int lane) {
+    return reinterpret_cast<const float2*>(row)[lane];
+}
+template <>
+__device__ __forceinline__ float2 ring_read<uint16_t>(const char* row, int lane) {
+    const uint32_t u = reinterpret_cast<const uint32_t*>(row)[lane];
+    return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
 }
 
-// psi^n at the wave's own cells (Heun stage 2).
-template <typename T, int TY>
-__device__ __forceinline__ void load_old(SArgs a, int k, const WaveCtx<TY>& w, float2 (&o)[TY]) {
-    const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_old) + (size_t)k * w.planeb, w.planeb);
-    const uint32_t row0 = (uint32_t)(w.y0 + kGhost) * w.pitchb;
-#pragma unroll
-    for (int t = 0; t < TY; ++t) o[t] = Store<T>::bload2(r, w.lane_off, row0 + t * w.pitchb);
+// The staged x-halo of one output row: cells -2, -1, 128, 129 of the tile
+// (the same address in every lane: a broadcast read).
+template <typename T>
+__device__ __forceinline__ float4 halo_read(const char* h);
+template <>
+__device__ __forceinline__ float4 halo_read<float>(const char* h) {
+    return *reinterpret_cast<const float4*>(h);
+}
+template <>
+__device__ __forceinline__ float4 halo_read<uint16_t>(const char* h) {
+    const uint2 u = *reinterpret_cast<const uint2*>(h);
+    return make_float4(bf16_widen(u.x & 0xffffu), bf16_widen(u.x >> 16), bf16_widen(u.y & 0xffffu),
+                       bf16_widen(u.y >> 16));
 }
 
 // Stores one cell pair (or the first cell only) at byte offset `off` of plane base `p`.
@@ -305,8 +393,8 @@ __device__ __forceinline__ void write_frame(SArgs a, const OrdConst& o, int k, i
 // Window row r holds grid row y0 - 2 + r; output row t is window row t + 2.
 template <int ORDER, int MODE, typename T, int TY, int W, bool SX, bool SY>
 __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k, WaveCtx<TY>& w,
-                                               const float2 (&win)[TY + 4], const float2 (&oldv)[TY],
-                                               double* facc) {
+                                               const float2 (&win)[TY + 4], const float4 (&halo)[TY],
+                                               const float2 (&oldv)[TY], double* facc) {
     constexpr int D = SY ? 0 : 1;  // y-traces of output row t: Ry[t + 1 + D] (south), Ry[t + 2 + D] (north)
     constexpr float HX = SX ? 0.5f : -0.5f;
     constexpr float HY = SY ? 0.5f : -0.5f;
@@ -335,22 +423,25 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
         const int j = w.y0 + t;
         if (j >= a.ny) break;  // wave-uniform
         const float c0 = win[t + 2].x, c1 = win[t + 2].y;
-        const float L = lane_from_left(c1);   // cell left of c0
-        const float Rn = lane_from_right(c0);  // cell right of c1
+        const float4 hv = halo[t];  // cells -2, -1 and 128, 129 of the tile
+        const float L = lane_from_left(c1, hv.y);    // cell left of c0 (lane 0: cell -1)
+        const float Rn = lane_from_right(c0, hv.z);  // cell right of c1 (lane 63: cell 128)
         float dRx0, dRx1, tW0, tE0, tE1;       // x-differences and traces (west of cell 1 = east of cell 0)
         if (ORDER == 2) {
             const float d01 = c1 - c0;
             const float m0 = minmod(c0 - L, d01), m1 = minmod(d01, Rn - c1);
             const float R0 = fmaf(HX, m0, c0), R1 = fmaf(HX, m1, c1);
             if (SX) {
-                const float Rl = lane_from_left(R1);
+                // lane 0: east-face value of cell -1 from the halo
+                const float Rl = lane_from_left(R1, fmaf(HX, minmod(hv.y - hv.x, c0 - hv.y), hv.y));
                 dRx0 = R0 - Rl;
                 dRx1 = R1 - R0;
                 tW0 = Rl;
                 tE0 = R0;
                 tE1 = R1;
             } else {
-                const float Rr = lane_from_right(R0);
+                // lane 63: west-face value of cell 128 from the halo
+                const float Rr = lane_from_right(R0, fmaf(HX, minmod(hv.z - c1, hv.w - hv.z), hv.z));
                 dRx0 = R1 - R0;
                 dRx1 = Rr - R1;
                 tW0 = R0;
@@ -414,8 +505,8 @@ using const_ord_ptr = const __attribute__((address_space(4))) OrdConst*;
 
 template <int ORDER, int MODE, typename T, int TY, int W>
 __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
-                                                 const float2 (&win)[TY + 4], const float2 (&oldv)[TY],
-                                                 double* facc) {
+                                                 const float2 (&win)[TY + 4], const float4 (&halo)[TY],
+                                                 const float2 (&oldv)[TY], double* facc) {
     const const_ord_ptr q = (const_ord_ptr)a.ord + k;
     OrdConst o;
     o.cx = q->cx;
@@ -427,10 +518,10 @@ __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
     o.fx = q->fx;
     o.fy = q->fy;
     switch (o.flags & 3) {
-    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, oldv, facc); break;
-    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, oldv, facc); break;
-    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, oldv, facc); break;
-    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, oldv, facc); break;
+    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, halo, oldv, facc); break;
+    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, halo, oldv, facc); break;
+    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, halo, oldv, facc); break;
+    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, halo, oldv, facc); break;
     }
 }
 
@@ -444,10 +535,10 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nwg) {
     return xcd < rem ? xcd * (per + 1) + q8 : rem * (per + 1) + (xcd - rem) * per + q8;
 }
 
-template <int TY, int W>
+template <typename T, int TY, int W, int MODE>
 struct StageLds {
     double red[W][kMaxQ];
-    float2 rows[2][RowStage<TY, W>::kRows][kWave];
+    alignas(16) char ring[Ring<T, TY, W, MODE>::kBytes];
 };
 
 // The work of logical workgroup `logical` of one stage launch: tile and
@@ -455,9 +546,9 @@ struct StageLds {
 // 2 n_rects FP64 accumulators per thread.
 template <int ORDER, int MODE, typename T, int TY, int W>
 __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_all,
-                                           StageLds<TY, W>& lds) {
+                                           StageLds<T, TY, W, MODE>& lds) {
+    using R = Ring<T, TY, W, MODE>;
     auto& red = lds.red;
-    auto& rows_lds = lds.rows;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -465,18 +556,52 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
     const int tile = logical / a.G;
     const int tx = tile % a.ntx;
     const int tyi = tile / a.ntx;
+    const int k0 = g * a.Mg;
+    const int k1 = min(k0 + a.Mg, a.M);
+    const int yw = tyi * W * TY;  // padded row of the workgroup's first staged row
+
+    if (wave == W) {  // the loader wave
+        const uint32_t es = (uint32_t)sizeof(T);
+        const uint32_t pitchb = (uint32_t)a.pitch * es;
+        const uint32_t planeb = (uint32_t)((size_t)a.plane * es);
+        const uint32_t tile_off = (uint32_t)(a.ox + tx * kTileX) * es;  // 128-byte aligned
+        // ordinates k0 .. k0 + kSlots - 2 in flight before the first barrier
+#pragma unroll
+        for (int d = 0; d < R::kSlots - 1; ++d)
+            if (k0 + d < k1)
+                ring_issue<T, TY, W, MODE>(a, k0 + d, yw, tile_off, pitchb, planeb, lds.ring + d * R::kSlotBytes);
+        __syncthreads();
+        int slot = 0;
+        for (int k = k0; k < k1; ++k) {
+            // ordinate k's copies are complete when at most the later
+            // ordinates' copies are still outstanding
+            const int ahead = min(R::kSlots - 2, k1 - 1 - k);
+            if (ahead >= 3) wait_vmcnt<R::wait_ahead(3)>();
+            else if (ahead == 2) wait_vmcnt<R::wait_ahead(2)>();
+            else if (ahead == 1) wait_vmcnt<R::wait_ahead(1)>();
+            else wait_vmcnt<0>();
+            __builtin_amdgcn_s_barrier();
+            // the slot of ordinate k - 1 is free now: ordinate k + kSlots - 1 goes there
+            const int s_free = slot == 0 ? R::kSlots - 1 : slot - 1;
+            if (k + R::kSlots - 1 < k1)
+                ring_issue<T, TY, W, MODE>(a, k + R::kSlots - 1, yw, tile_off, pitchb, planeb,
+                                           lds.ring + s_free * R::kSlotBytes);
+            slot = slot == R::kSlots - 1 ? 0 : slot + 1;
+        }
+        __syncthreads();
+        return;
+    }
 
     WaveCtx<TY> w;
     w.y0 = (tyi * W + wave) * TY;
-    const int pc = tx * kTileX + 2 * lane;  // padded column of the lane's first cell
-    w.i0 = pc - kGhost;
-    const int pcc = min(pc, a.pitch - 2);   // keep halo lanes of the last tile inside the row
+    w.i0 = tx * kTileX + 2 * lane;          // interior column of the lane's first cell
+    const int pc = a.ox + w.i0;             // its column in the padded row
+    const int pcc = min(pc, a.pitch - 2);   // lanes past the last column stay inside the row
     w.lane_off = (uint32_t)pcc * (uint32_t)sizeof(T);
     w.pitchb = (uint32_t)a.pitch * (uint32_t)sizeof(T);
     w.planeb = (uint32_t)((size_t)a.plane * sizeof(T));
-    const bool out_lane = lane >= 1 && lane <= kWave - 2;
-    w.v0 = out_lane && w.i0 < a.nx;
-    w.v1 = out_lane && w.i0 + 1 < a.nx;
+    w.v0 = w.i0 < a.nx;
+    w.v1 = w.i0 + 1 < a.nx;
     w.store_off = w.v1 ? w.lane_off : kDropOffset;
     w.single_off = (w.v0 && !w.v1) ? w.lane_off : kDropOffset;
     w.ragged = __any(w.v0 && !w.v1);
@@ -484,10 +609,10 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         const uint32_t es = (uint32_t)sizeof(T);
         const bool holds_w = w.v0 && w.i0 == 0;
         const bool holds_e0 = w.v0 && w.i0 == a.nx - 1, holds_e1 = w.v1 && w.i0 + 1 == a.nx - 1;
-        w.gw1 = holds_w ? 1 * es : kDropOffset;
-        w.gw2 = holds_w ? 0 : kDropOffset;
-        w.ge1 = (holds_e0 || holds_e1) ? (uint32_t)(a.nx + kGhost) * es : kDropOffset;
-        w.ge2 = (holds_e0 || holds_e1) ? (uint32_t)(a.nx + kGhost + 1) * es : kDropOffset;
+        w.gw1 = holds_w ? (uint32_t)(a.ox - 1) * es : kDropOffset;
+        w.gw2 = holds_w ? (uint32_t)(a.ox - 2) * es : kDropOffset;
+        w.ge1 = (holds_e0 || holds_e1) ? (uint32_t)(a.ox + a.nx) * es : kDropOffset;
+        w.ge2 = (holds_e0 || holds_e1) ? (uint32_t)(a.ox + a.nx + 1) * es : kDropOffset;
         w.ge_first = holds_e0;
         w.ghost_wave = MODE != kQoiOnly && (__any(holds_w || holds_e0 || holds_e1) || w.y0 == 0 ||
                                             (w.y0 <= a.ny - 1 && a.ny - 1 < w.y0 + TY));
@@ -547,60 +672,23 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
     w.any_tag = __any(my_tags != 0);
 
     {
-        const int k0 = g * a.Mg;
-        const int k1 = min(k0 + a.Mg, a.M);
-        const int yw = tyi * W * TY;  // padded row of the workgroup's first staged row
-        // Rows of ordinates k + 1 and k + 2 are in flight in registers (preA /
-        // preB, alternating) while ordinate k is computed from LDS; a row set
-        // is committed to LDS one iteration before it is used, and one barrier
-        // per ordinate separates the two LDS buffers.
-        float2 preA[RowStage<TY, W>::kPer], preB[RowStage<TY, W>::kPer], ocur[TY], onext[TY];
+        __syncthreads();  // set-up done; the loader's first copies are in flight
+        int slot = 0;
+        for (int k = k0; k < k1; ++k) {
+            __syncthreads();  // ordinate k's rows are in slot `slot`
+            const char* sb = lds.ring + slot * R::kSlotBytes;
+            float2 win[TY + 4], oldv[TY];
+            float4 halo[TY];
 #pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            ocur[t] = make_float2(0.0f, 0.0f);
-            onext[t] = make_float2(0.0f, 0.0f);
-        }
-        stage_issue<T, TY, W>(a, k0, yw, wave, w, preA);
-        if (k0 + 1 < k1) stage_issue<T, TY, W>(a, k0 + 1, yw, wave, w, preB);
-        stage_commit<TY, W>(rows_lds[0], wave, lane, preA);
-        if (MODE == kAverage) load_old<T, TY>(a, k0, w, ocur);
-        __syncthreads();
-        for (int k = k0; k < k1; k += 2) {
-            // even offset: ordinate k from buffer 0; preB holds k + 1
-            if (k + 2 < k1) stage_issue<T, TY, W>(a, k + 2, yw, wave, w, preA);
-            if (MODE == kAverage && k + 1 < k1) load_old<T, TY>(a, k + 1, w, onext);
-            {
-                float2 win[TY + 4];
+            for (int r = 0; r < TY + 4; ++r) win[r] = ring_read<T>(sb + (wave * TY + r) * R::kRowBytes, lane);
 #pragma unroll
-                for (int r = 0; r < TY + 4; ++r) win[r] = rows_lds[0][wave * TY + r][lane];
-                process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, ocur, facc);
-            }
-            if (k + 1 < k1) {
-                stage_commit<TY, W>(rows_lds[1], wave, lane, preB);
-                if (MODE == kAverage) {
+            for (int t = 0; t < TY; ++t) halo[t] = halo_read<T>(sb + R::kHaloOffset + (wave * TY + t) * R::kHaloRowBytes);
 #pragma unroll
-                    for (int t = 0; t < TY; ++t) ocur[t] = onext[t];
-                }
-            }
-            __syncthreads();
-            if (k + 1 >= k1) break;  // workgroup-uniform
-            // odd offset: ordinate k + 1 from buffer 1; preA holds k + 2
-            if (k + 3 < k1) stage_issue<T, TY, W>(a, k + 3, yw, wave, w, preB);
-            if (MODE == kAverage && k + 2 < k1) load_old<T, TY>(a, k + 2, w, onext);
-            {
-                float2 win[TY + 4];
-#pragma unroll
-                for (int r = 0; r < TY + 4; ++r) win[r] = rows_lds[1][wave * TY + r][lane];
-                process_ordinate<ORDER, MODE, T, TY, W>(a, k + 1, w, win, ocur, facc);
-            }
-            if (k + 2 < k1) {
-                stage_commit<TY, W>(rows_lds[0], wave, lane, preA);
-                if (MODE == kAverage) {
-#pragma unroll
-                    for (int t = 0; t < TY; ++t) ocur[t] = onext[t];
-                }
-            }
-            __syncthreads();
+            for (int t = 0; t < TY; ++t)
+                oldv[t] = MODE == kAverage ? ring_read<T>(sb + (R::kOldRow0 + wave * TY + t) * R::kRowBytes, lane)
+                                           : make_float2(0.0f, 0.0f);
+            process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, halo, oldv, facc);
+            slot = slot == R::kSlots - 1 ? 0 : slot + 1;
         }
         if (MODE != kQoiOnly) {
             char* pphi = reinterpret_cast<char*>(a.phi_part + (size_t)g * (size_t)a.plane);
@@ -631,18 +719,11 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
 }
 
 // ---------------------------------------------------------------- stage kernels
-// Occupancy each mode is compiled for (waves per SIMD): the update stage fits
-// 80 VGPRs (6 waves), the averaging stage keeps psi^n in flight too (5).
-template <int MODE, int TY>
-struct WavesPerEu {
-    static constexpr int value = TY > 2 ? 3 : (MODE == kUpdate ? 6 : (MODE == kAverage ? 5 : 8));
-};
-
+// Workgroup: W compute waves + 1 loader wave.
 template <int ORDER, int MODE, typename T, int TY, int W>
-__global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(WavesPerEu<MODE, TY>::value)))
-sn_stage_kernel(const StageArgs a) {
+__global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_kernel(const StageArgs a) {
     extern __shared__ double facc_all[];  // [2 n_rects][kWave W] per-thread FP64 face accumulators
-    __shared__ StageLds<TY, W> lds;
+    __shared__ StageLds<T, TY, W, MODE> lds;
     stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, xcd_contiguous(blockIdx.x, gridDim.x), facc_all, lds);
 }
 
@@ -662,10 +743,9 @@ __device__ __forceinline__ int find_instance(const int32_t* first, int n, int it
 // One stage of many instances in one persistent launch: the grid strides over
 // the concatenated workgroup lists of the selected instances.
 template <int ORDER, int MODE, typename T, int TY, int W>
-__global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(WavesPerEu<kAverage, TY>::value)))
-sn_stage_batch_kernel(const BatchLaunch L) {
+__global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_batch_kernel(const BatchLaunch L) {
     extern __shared__ double facc_all[];
-    __shared__ StageLds<TY, W> lds;
+    __shared__ StageLds<T, TY, W, MODE> lds;
     using ci32 = const __attribute__((address_space(4))) int32_t*;
     const int pos = xcd_contiguous(blockIdx.x, gridDim.x);
     for (int base = 0; base < L.total; base += gridDim.x) {
@@ -682,16 +762,15 @@ sn_stage_batch_kernel(const BatchLaunch L) {
 template <int ORDER, int MODE, typename T, int TY>
 static void launch_w(int waves, const StageArgs& a, hipStream_t s) {
     const size_t lds_per_thread = (size_t)2 * a.n_rects * sizeof(double);
-    switch (waves) {
-    case 4: hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 4>), dim3(a.n_wg), dim3(kWave * 4), lds_per_thread * kWave * 4, s, a); break;
-    case 8: hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 8>), dim3(a.n_wg), dim3(kWave * 8), lds_per_thread * kWave * 8, s, a); break;
-    default: hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 16>), dim3(a.n_wg), dim3(kWave * 16), lds_per_thread * kWave * 16, s, a); break;
-    }
+    if (waves == 4)
+        hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 4>), dim3(a.n_wg), dim3(kWave * 5), lds_per_thread * kWave * 4, s, a);
+    else
+        hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 8>), dim3(a.n_wg), dim3(kWave * 9), lds_per_thread * kWave * 8, s, a);
 }
 
 template <int ORDER, typename T>
 static hipError_t launch_stage_tu(int mode, int rows, int waves, const StageArgs& a, hipStream_t s) {
-    if (waves != 4 && waves != 8 && waves != 16) return hipErrorInvalidValue;
+    if (waves != 4 && waves != 8) return hipErrorInvalidValue;
     if (rows == 2) {
         if (mode == kUpdate) launch_w<ORDER, kUpdate, T, 2>(waves, a, s);
         else if (mode == kAverage) launch_w<ORDER, kAverage, T, 2>(waves, a, s);
@@ -730,23 +809,20 @@ static void launch_batch_shape(const BatchLaunch& L, int wgs_per_cu, int cus, in
     static int resident[kMaxRects + 1] = {};  // per face-accumulator size, filled on first use
     const size_t lds = (size_t)2 * max_rects * sizeof(double) * kWave * W;
     auto kern = sn_stage_batch_kernel<ORDER, MODE, T, TY, W>;
-    const int grid = batch_grid(kern, kWave * W, lds, L.total, wgs_per_cu, cus, &resident[max_rects]);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * W), lds, s, L);
+    const int grid = batch_grid(kern, kWave * (W + 1), lds, L.total, wgs_per_cu, cus, &resident[max_rects]);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * (W + 1)), lds, s, L);
 }
 
 template <int ORDER, int MODE, typename T, int TY>
 static void launch_batch_w(int waves, const BatchLaunch& L, int wgs_per_cu, int cus, int max_rects, hipStream_t s) {
-    switch (waves) {
-    case 4: launch_batch_shape<ORDER, MODE, T, TY, 4>(L, wgs_per_cu, cus, max_rects, s); break;
-    case 8: launch_batch_shape<ORDER, MODE, T, TY, 8>(L, wgs_per_cu, cus, max_rects, s); break;
-    default: launch_batch_shape<ORDER, MODE, T, TY, 16>(L, wgs_per_cu, cus, max_rects, s); break;
-    }
+    if (waves == 4) launch_batch_shape<ORDER, MODE, T, TY, 4>(L, wgs_per_cu, cus, max_rects, s);
+    else launch_batch_shape<ORDER, MODE, T, TY, 8>(L, wgs_per_cu, cus, max_rects, s);
 }
 
 template <int ORDER, typename T>
 static hipError_t launch_batch_tu(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
                                   int max_rects, hipStream_t s) {
-    if (waves != 4 && waves != 8 && waves != 16) return hipErrorInvalidValue;
+    if (waves != 4 && waves != 8) return hipErrorInvalidValue;
     if (mode != kUpdate && mode != kAverage) return hipErrorInvalidValue;
     if (max_rects < 0 || max_rects > kMaxRects) return hipErrorInvalidValue;
     if (rows == 2) {

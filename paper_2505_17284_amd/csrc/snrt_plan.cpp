@@ -195,13 +195,16 @@ sn_status derive(sn_plan* P, int group_size, int rows, int waves) {
     P->elem = P->dtype == SN_F32 ? 4 : 2;
     // Rows of 64-byte multiples holding the interior plus the two-cell ghost
     // frame; enough rows that every window of the last row of tiles is inside.
-    const int align_elems = (int)(64 / P->elem);
-    P->pitch = (P->nx + 2 * kGhost + align_elems - 1) / align_elems * align_elems;
+    // Rows of whole 128-byte lines; the interior starts one line in (ox
+    // columns), so that 128-column tiles are line-aligned.
+    const int line_elems = (int)(128 / P->elem);
+    P->ox = line_elems;
+    P->pitch = (P->ox + P->nx + kGhost + line_elems - 1) / line_elems * line_elems;
     P->ntx = (P->nx + kTileX - 1) / kTileX;
     P->nty = (P->ny + wv * rw - 1) / (wv * rw);
     P->ny_alloc = P->nty * wv * rw + 2 * kGhost;
     P->plane = (int64_t)P->ny_alloc * P->pitch;
-    P->origin = (int64_t)kGhost * P->pitch + kGhost;
+    P->origin = (int64_t)kGhost * P->pitch + P->ox;
     if ((uint64_t)P->plane * P->elem >= (1ull << 31))
         return fail(SN_ERR_UNSUPPORTED, "one psi plane exceeds 2 GiB (grid %d x %d)", P->nx, P->ny);
     const int64_t n_wg = (int64_t)P->ntx * P->nty * P->G;
@@ -291,6 +294,7 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
     a.ny = P->ny;
     a.pitch = P->pitch;
     a.M = P->M;
+    a.ox = P->ox;
     a.G = P->G;
     a.Mg = P->Mg;
     a.ntx = P->ntx;
@@ -314,6 +318,7 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.ny = P->ny;
     f.pitch = P->pitch;
     f.G = P->G;
+    f.ox = P->ox;
     f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
     f.qpart = P->sp<double>(P->off_qpart);
     f.scale = P->sp<double>(P->off_scale);
@@ -337,6 +342,7 @@ GhostArgs ghost_args(const sn_plan* P, char* psi) {
     ga.ny = P->ny;
     ga.pitch = P->pitch;
     ga.M = P->M;
+    ga.ox = P->ox;
     for (int side = 0; side < 4; ++side) {
         ga.bc[side] = P->bc[side];
         ga.ghost[side] = P->bc[side] == SN_BC_INFLOW ? (float)P->inflow[side] : 0.0f;
@@ -596,6 +602,7 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
         pa.ny = P->ny;
         pa.pitch = P->pitch;
         pa.M = P->M;
+        pa.ox = P->ox;
         HIP_TRY(launch_phi_init(P->dtype, pa, s), "phi init launch");
     }
     // Ghost frames of both buffers: B's incoming vacuum/inflow ghosts are

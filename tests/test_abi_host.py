@@ -120,7 +120,7 @@ def test_buffer_sizes(L):
     assert info["psi_bytes"] >= 256 * 700 * info["pitch"] * 4
     assert info["psi_bytes"] % 256 == 0 and info["scratch_bytes"] % 256 == 0
     bf = solver.plan_info(I.config(2).replace(psi_dtype="bf16"))
-    assert bf["psi_bytes"] < info["psi_bytes"] * 0.51
+    assert bf["psi_bytes"] < info["psi_bytes"] * 0.55  # BF16 rows start one 128-byte line in too
 
 
 def test_calls_in_wrong_order_fail_cleanly(L):

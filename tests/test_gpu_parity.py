@@ -99,7 +99,7 @@ def test_degenerate_and_tile_edge_shapes(sv, orc, shape, order):
 
 
 @pytest.mark.parametrize("rows", [2, 4])
-@pytest.mark.parametrize("waves", [4, 8, 16])
+@pytest.mark.parametrize("waves", [4, 8])
 @pytest.mark.parametrize("group", [1, 5, 32])
 def test_launch_shapes_agree(sv, orc, rows, waves, group):
     """Every compiled launch shape (rows per wave, waves per workgroup) and
