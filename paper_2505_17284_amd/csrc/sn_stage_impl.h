@@ -235,8 +235,8 @@ struct Ring {
     static constexpr int kRows = W * TY + 4;                             // stencil rows
     static constexpr int kOldRows = MODE == kAverage ? W * TY : 0;       // psi^n rows
     static constexpr int kRowBytes = kWave * 2 * (int)sizeof(T);         // 128 cells
-    static constexpr int kDmaBytes = sizeof(T) == 4 ? 16 : 4;            // bytes per lane per copy
-    static constexpr int kRowsPerDma = kWave * kDmaBytes / kRowBytes;    // 2 (f32) or 1 (bf16)
+    static constexpr int kDmaBytes = 16;                                   // bytes per lane per copy
+    static constexpr int kRowsPerDma = kWave * kDmaBytes / kRowBytes;    // 2 (f32) or 4 (bf16)
     static constexpr int kLanesPerRow = kWave / kRowsPerDma;
     static constexpr int kDmaStencil = (kRows + kRowsPerDma - 1) / kRowsPerDma;
     static constexpr int kDmaOld = (kOldRows + kRowsPerDma - 1) / kRowsPerDma;
@@ -268,45 +268,67 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Loader: ordinate k's rows into ring slot `slot`. Lane l copies kDmaBytes at
-// column offset (l % kLanesPerRow) kDmaBytes of row l / kLanesPerRow of each
-// kRowsPerDma-row block; the LDS copy lands at the block's base + l kDmaBytes,
-// i.e. row-major [row][128 cells], the layout the compute lanes read.
+// Per-lane byte offsets of the loader's copies within a row, fixed for the
+// whole launch. Copies of columns no output cell of the tile depends on (past
+// the east ghost cells of the grid, or past the interior for psi^n) carry the
+// dropped offset and fetch nothing.
+struct LoaderOffsets {
+    uint32_t stencil;  // rows of the stage input
+    uint32_t old;      // rows of psi^n (averaging stage)
+    uint32_t halo;     // x-halo dwords of the output rows
+};
+
+// Lane l copies kDmaBytes at column offset (l % kLanesPerRow) kDmaBytes of
+// row l / kLanesPerRow of each kRowsPerDma-row block; the LDS copy lands at
+// the block's base + l kDmaBytes, i.e. row-major [row][128 cells], the layout
+// the compute lanes read. The x-halo dwords: lane l covers dword
+// (l % kHaloLanesPerRow) of output row l / kHaloLanesPerRow, the first half
+// of a row's dwords left of the tile, the rest right of it.
 template <typename T, int TY, int W, int MODE>
-__device__ __forceinline__ void ring_issue(SArgs a, int k, int yw, uint32_t tile_off, uint32_t pitchb,
-                                           uint32_t planeb, char* slot) {
+__device__ __forceinline__ LoaderOffsets loader_offsets(SArgs a, int col0, uint32_t tile_off, uint32_t pitchb) {
     using R = Ring<T, TY, W, MODE>;
+    constexpr int kCellsPerCopy = R::kDmaBytes / (int)sizeof(T);
     const int lane = threadIdx.x & (kWave - 1);
+    LoaderOffsets o;
+    const int c = col0 + (lane % R::kLanesPerRow) * kCellsPerCopy;  // interior column of the copy's first cell
     const uint32_t voff = tile_off + (uint32_t)(lane % R::kLanesPerRow) * R::kDmaBytes +
                           (uint32_t)(lane / R::kLanesPerRow) * pitchb;
+    o.stencil = c < a.nx + kGhost ? voff : kDropOffset;
+    o.old = c < a.nx ? voff : kDropOffset;
+    const int e = lane % R::kHaloLanesPerRow, hr = lane / R::kHaloLanesPerRow;
+    const int half = R::kHaloLanesPerRow / 2;
+    // rows past the workgroup's output rows, and east cells past the grid's
+    // ghost cells, are not needed
+    const bool right_needed = col0 + kTileX < a.nx + kGhost;
+    o.halo = hr >= W * TY || (e >= half && !right_needed)
+                 ? kDropOffset
+                 : (e < half ? tile_off - 2 * (uint32_t)sizeof(T) + 4 * e
+                             : tile_off + (uint32_t)(kTileX * sizeof(T)) + 4 * (e - half)) +
+                       (uint32_t)hr * pitchb;
+    return o;
+}
+
+// Loader: ordinate k's rows into ring slot `slot`.
+template <typename T, int TY, int W, int MODE>
+__device__ __forceinline__ void ring_issue(SArgs a, int k, int yw, const LoaderOffsets& lo, uint32_t pitchb,
+                                           uint32_t planeb, char* slot) {
+    using R = Ring<T, TY, W, MODE>;
     const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_in) + (size_t)k * planeb, planeb);
 #pragma unroll
     for (int i = 0; i < R::kDmaStencil; ++i)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(slot + i * R::kRowsPerDma * R::kRowBytes),
-                                                 R::kDmaBytes, voff, (uint32_t)(yw + i * R::kRowsPerDma) * pitchb,
-                                                 0, 0);
-    {
-        // x-halo: lane l covers dword (l % kHaloLanesPerRow) of output row l / kHaloLanesPerRow;
-        // the first half of a row's dwords sit left of the tile, the rest right
-        const int e = lane % R::kHaloLanesPerRow, hr = lane / R::kHaloLanesPerRow;
-        const int half = R::kHaloLanesPerRow / 2;
-        // rows past the workgroup's output rows are not needed: their copies
-        // carry the out-of-range offset and fetch nothing
-        const uint32_t hoff = hr >= W * TY ? kDropOffset
-                                           : (e < half ? tile_off - 2 * (uint32_t)sizeof(T) + 4 * e
-                                                       : tile_off + (uint32_t)(kTileX * sizeof(T)) + 4 * (e - half)) +
-                                                 (uint32_t)hr * pitchb;
+                                                 R::kDmaBytes, lo.stencil,
+                                                 (uint32_t)(yw + i * R::kRowsPerDma) * pitchb, 0, 0);
 #pragma unroll
-        for (int i = 0; i < R::kDmaHalo; ++i)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(slot + R::kHaloOffset + i * kWave * 4), 4, hoff,
-                                                     (uint32_t)(yw + kGhost + i * R::kHaloRowsPerDma) * pitchb, 0, 0);
-    }
+    for (int i = 0; i < R::kDmaHalo; ++i)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(slot + R::kHaloOffset + i * kWave * 4), 4, lo.halo,
+                                                 (uint32_t)(yw + kGhost + i * R::kHaloRowsPerDma) * pitchb, 0, 0);
     if (MODE == kAverage) {
         const rsrc_t ro = make_rsrc(static_cast<const char*>(a.psi_old) + (size_t)k * planeb, planeb);
 #pragma unroll
         for (int i = 0; i < R::kDmaOld; ++i)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                ro, (lds_ptr)(slot + (R::kOldRow0 + i * R::kRowsPerDma) * R::kRowBytes), R::kDmaBytes, voff,
+                ro, (lds_ptr)(slot + (R::kOldRow0 + i * R::kRowsPerDma) * R::kRowBytes), R::kDmaBytes, lo.old,
                 (uint32_t)(yw + kGhost + i * R::kRowsPerDma) * pitchb, 0, 0);
     }
 }
@@ -565,11 +587,12 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         const uint32_t pitchb = (uint32_t)a.pitch * es;
         const uint32_t planeb = (uint32_t)((size_t)a.plane * es);
         const uint32_t tile_off = (uint32_t)(a.ox + tx * kTileX) * es;  // 128-byte aligned
+        const LoaderOffsets lo = loader_offsets<T, TY, W, MODE>(a, tx * kTileX, tile_off, pitchb);
         // ordinates k0 .. k0 + kSlots - 2 in flight before the first barrier
 #pragma unroll
         for (int d = 0; d < R::kSlots - 1; ++d)
             if (k0 + d < k1)
-                ring_issue<T, TY, W, MODE>(a, k0 + d, yw, tile_off, pitchb, planeb, lds.ring + d * R::kSlotBytes);
+                ring_issue<T, TY, W, MODE>(a, k0 + d, yw, lo, pitchb, planeb, lds.ring + d * R::kSlotBytes);
         __syncthreads();
         int slot = 0;
         for (int k = k0; k < k1; ++k) {
@@ -584,7 +607,7 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
             // the slot of ordinate k - 1 is free now: ordinate k + kSlots - 1 goes there
             const int s_free = slot == 0 ? R::kSlots - 1 : slot - 1;
             if (k + R::kSlots - 1 < k1)
-                ring_issue<T, TY, W, MODE>(a, k + R::kSlots - 1, yw, tile_off, pitchb, planeb,
+                ring_issue<T, TY, W, MODE>(a, k + R::kSlots - 1, yw, lo, pitchb, planeb,
                                            lds.ring + s_free * R::kSlotBytes);
             slot = slot == R::kSlots - 1 ? 0 : slot + 1;
         }
