@@ -98,6 +98,42 @@ def cpu_baseline(problem, budget_s=15.0):
                       f"(FP64, {threads} OpenMP threads, {secs:.1f} s)"}
 
 
+def time_cavity(steps, dtype, warmup=3):
+    """Heun steps of the full-size walled cavity (1300^2 cells, 512 ordinates,
+    3.5 GB per FP32 psi buffer): the same kernels on a state far larger than
+    the 256 MB Infinity Cache."""
+    import torch
+
+    from paper_2505_17284_amd import inputs as I
+    from paper_2505_17284_amd import solver
+
+    p = I.config(3).replace(psi_dtype=dtype)
+    print(f"[bench] cavity: {p.name} {steps} steps", file=sys.stderr, flush=True)
+    plan = solver.Plan(p, device="cuda:0")
+    try:
+        plan.run(warmup, unbounded=True)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        t0 = time.perf_counter()
+        plan.run(steps, unbounded=True)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ms, counts = plan.kernel_ms()
+        plan.set_timing(False)
+        info = plan.info
+    finally:
+        plan.close()
+    s2 = ms[2] / max(counts[2], 1)
+    s1 = ms[1] / max(counts[1], 1)
+    b2 = algorithmic_bytes(p, info, 2)
+    b1 = algorithmic_bytes(p, info, 1)
+    return {"workload": "cavity1300_M512_heun2", "steps": steps, "ms_per_step": secs * 1e3 / steps,
+            "updates_per_s": p.cell_ordinates * steps / secs, "stage2_kernel_ms": s2,
+            "stage2_achieved_GBs": b2 / (s2 * 1e-3) / 1e9, "stage2_frac": b2 / (s2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "stage1_kernel_ms": s1, "stage1_achieved_GBs": b1 / (s1 * 1e-3) / 1e9,
+            "step_algorithmic_GBs": (b1 + b2) / (secs / steps) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +150,8 @@ def main():
                     help="requests of the serving comparison (0 skips it)")
     ap.add_argument("--serving-load", type=float, default=0.9,
                     help="arrival rate as a fraction of the one-at-a-time capacity")
+    ap.add_argument("--cavity-steps", type=int, default=40,
+                    help="Heun steps timed on the full-size walled cavity, 1300^2 x 512 ordinates (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -199,6 +237,8 @@ def main():
         torch.cuda.synchronize()
         line["calibration_copy_bytes"] = n
         del src, dst
+    if args.cavity_steps:
+        line["cavity"] = time_cavity(args.cavity_steps, args.dtype)
     from paper_2505_17284_amd import serve
 
     if args.uq:

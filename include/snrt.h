@@ -240,10 +240,18 @@ typedef struct sn_batch_opts {
                                 * many workgroups per compute unit striding
                                 * over the tiles, -1 = a persistent grid of as
                                 * many as are resident at once */
-    uint64_t cache_group_bytes; /* plans whose two psi buffers fit this size
-                                 * are packed into groups of at most this many
-                                 * bytes that take their steps of a run back to
-                                 * back (cache reuse); 0 = 64 MiB */
+    uint64_t cache_group_bytes; /* > 0: plans whose two psi buffers fit this
+                                 * size are packed into groups of at most this
+                                 * many bytes that take their steps of a run
+                                 * back to back (cache reuse, fewer workgroups
+                                 * per launch); 0 (default): every unfinished
+                                 * plan takes each stage in one launch */
+    int32_t direct_min_workgroups; /* plans with at least this many workgroups
+                                    * per stage fill the GPU on their own and
+                                    * take their stages as launches of their
+                                    * own (kernel arguments, no instance
+                                    * lookup); smaller plans share the batched
+                                    * launch. 0 = 4 per compute unit, -1 = never */
 } sn_batch_opts;
 
 typedef struct sn_batch_info {
@@ -277,9 +285,11 @@ sn_status sn_batch_admit(sn_batch *batch, sn_plan *plan, int32_t *slot);
 sn_status sn_batch_run(sn_batch *batch, int32_t n_steps, void *stream);
 
 /* Per-slot step quota: in every later sn_batch_run the slot advances at most
- * `steps` steps (1 .. max_steps_per_run; 0 removes the quota). A scheduler
- * uses it to share the GPU by work rather than by steps (cheap problems take
- * more steps per run than expensive ones). */
+ * `steps` steps (1 .. max_steps_per_run; 0 removes the quota;
+ * SN_STEPS_PAUSED keeps the slot's state where it is until the quota is set
+ * again). A scheduler uses it to share the GPU by work rather than by steps,
+ * or to give the oldest request full runs and let later ones fill in. */
+#define SN_STEPS_PAUSED (-1)
 sn_status sn_batch_set_steps(sn_batch *batch, int32_t slot, int32_t steps);
 
 /* Host view of a slot: done = (step == N_t). The QoIs of the plan come from

@@ -79,7 +79,7 @@ class SnBatchOpts(ctypes.Structure):
         ("max_instances", _i32), ("max_steps_per_run", _i32), ("order", _i32), ("stepper", _i32),
         ("psi_dtype", _i32), ("rows_per_wave", _i32), ("waves_per_group", _i32),
         ("hbm_budget_bytes", ctypes.c_uint64), ("use_graph", _i32), ("workgroups_per_cu", _i32),
-        ("cache_group_bytes", ctypes.c_uint64),
+        ("cache_group_bytes", ctypes.c_uint64), ("direct_min_workgroups", _i32),
     ]
 
 

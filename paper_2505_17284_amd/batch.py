@@ -25,6 +25,9 @@ from . import solver
 from ._lib import SN_BF16, SN_ERR_BUSY, SN_F32, SnBatchInfo, SnBatchOpts, SnError, check, lib
 
 
+PAUSED = -1  # step quota of a slot that takes no steps (SN_STEPS_PAUSED)
+
+
 class Busy(RuntimeError):
     """No free slot or not enough budget for the problem right now."""
 
@@ -39,14 +42,15 @@ class Batch:
     def __init__(self, order: int = 2, stepper: int = 1, psi_dtype: str = "f32", max_instances: int = 256,
                  steps_per_run: int = 16, rows_per_wave: int = 2, waves_per_group: int = 4,
                  hbm_budget_bytes: int = 0, use_graph: bool = True, workgroups_per_cu: int = 0,
-                 cache_group_bytes: int = 0, device: str = "cuda:0"):
+                 cache_group_bytes: int = 0, direct_min_workgroups: int = 0, device: str = "cuda:0"):
         torch = solver._torch()
         self.device = torch.device(device)
         self.opts = SnBatchOpts(max_instances=max_instances, max_steps_per_run=steps_per_run, order=order,
                                 stepper=stepper, psi_dtype=SN_BF16 if psi_dtype == "bf16" else SN_F32,
                                 rows_per_wave=rows_per_wave, waves_per_group=waves_per_group,
                                 hbm_budget_bytes=hbm_budget_bytes, use_graph=1 if use_graph else 0,
-                                workgroups_per_cu=workgroups_per_cu, cache_group_bytes=cache_group_bytes)
+                                workgroups_per_cu=workgroups_per_cu, cache_group_bytes=cache_group_bytes,
+                                direct_min_workgroups=direct_min_workgroups)
         self.psi_dtype = psi_dtype
         self.steps_per_run = steps_per_run
         nbytes = ctypes.c_uint64()
@@ -101,8 +105,12 @@ class Batch:
         n = self.steps_per_run if n_steps is None else int(n_steps)
         check(lib().sn_batch_run(self.h, n, self.stream), "sn_batch_run")
 
+    def synchronize(self):
+        """Wait for every run issued so far."""
+        solver._torch().cuda.synchronize(self.device)
+
     def set_steps(self, slot: int, steps: int):
-        """Most steps the slot takes per run (0 = no quota)."""
+        """Most steps the slot takes per run (0 = no quota, PAUSED = none until set again)."""
         check(lib().sn_batch_set_steps(self.h, slot, int(steps)), "sn_batch_set_steps")
 
     def status(self, slot: int):
@@ -176,4 +184,4 @@ def solve_all(problems, max_instances: int | None = None, steps_per_run: int = 1
         b.close()
 
 
-__all__ = ["Batch", "Busy", "footprint", "solve_all", "SnError"]
+__all__ = ["Batch", "Busy", "PAUSED", "footprint", "solve_all", "SnError"]

@@ -169,10 +169,10 @@ __global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs
 
 // Finalize of many instances in one persistent launch.
 __global__ void __launch_bounds__(256) sn_finalize_batch_kernel(const FinalizeBatch L) {
-    using ci32 = const __attribute__((address_space(4))) int32_t*;
+    __shared__ int inst[2];
     for (int item = blockIdx.x; item < L.total; item += gridDim.x) {
-        const int j = find_instance(L.first, L.n_sel, item);
-        finalize_block(*(FArgsPtr)(L.args + ((ci32)L.sel)[j]), item - ((ci32)L.first)[j]);
+        const InstanceRef r = find_instance(L.first, L.sel, L.n_sel, item, inst);
+        finalize_block(*(FArgsPtr)(L.args + r.sel), item - r.first);
     }
 }
 

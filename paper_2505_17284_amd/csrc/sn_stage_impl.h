@@ -219,18 +219,25 @@ struct WaveCtx {
 // A workgroup is W compute waves stacked in y plus one loader wave. For every
 // ordinate the loader copies the workgroup's W TY + 4 stencil rows (and, for
 // the averaging stage, the W TY rows of psi^n) from HBM straight into a ring
-// of kSlots LDS slots (buffer loads with an LDS destination), two ordinates
-// ahead of the compute waves; one barrier per ordinate hands a slot over. The
-// compute waves issue no global loads in the ordinate loop and the loader no
-// stores, so neither waits on the other's memory traffic (the wait counters
-// are per wave).
+// of kSlots LDS slots (buffer loads with an LDS destination), kSlots - 1
+// ordinates ahead of the compute waves; one barrier per ordinate hands a slot
+// over. The compute waves issue no global loads in the ordinate loop and the
+// loader no stores, so neither waits on the other's memory traffic (the wait
+// counters are per wave). The depth is set by the latency of a copy under
+// full load (several microseconds), not by its bytes: the stages without
+// psi^n rows keep 4 ordinates in flight, the averaging stage, whose slots
+// are almost twice as large, 2, both in ~32 KB of LDS per workgroup (4
+// workgroups per compute unit).
 #ifndef SN_RING_SLOTS
 #define SN_RING_SLOTS 3
+#endif
+#ifndef SN_RING_SLOTS_NO_OLD
+#define SN_RING_SLOTS_NO_OLD 5
 #endif
 
 template <typename T, int TY, int W, int MODE>
 struct Ring {
-    static constexpr int kSlots = SN_RING_SLOTS;  // ordinates in flight + the one being computed
+    static constexpr int kSlots = MODE == kAverage ? SN_RING_SLOTS : SN_RING_SLOTS_NO_OLD;  // in flight + computed
     static_assert(kSlots >= 2 && kSlots <= 5, "ring depth");
     static constexpr int kRows = W * TY + 4;                             // stencil rows
     static constexpr int kOldRows = MODE == kAverage ? W * TY : 0;       // psi^n rows
@@ -750,17 +757,42 @@ __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_kernel(const StageAr
     stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, xcd_contiguous(blockIdx.x, gridDim.x), facc_all, lds);
 }
 
-// Index j of the selected instance holding item: first[j] <= item < first[j + 1].
-__device__ __forceinline__ int find_instance(const int32_t* first, int n, int item) {
-    using ci32 = const __attribute__((address_space(4))) int32_t*;
-    const ci32 f = (ci32)first;
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (f[mid] <= item) lo = mid;
-        else hi = mid;
+// The selected instance j holding item (first[j] <= item < first[j + 1]):
+// returns its argument index sel[j] and its first item first[j]. Wave 0 tests
+// 64 candidates per round, loading first[] and sel[] together with
+// independent vector loads and taking the hit from a ballot (a binary search
+// would chain dependent scalar loads at the start of every workgroup), and
+// passes the pair to the other waves through LDS. The first barrier orders
+// every LDS use of the previous item (the pair included) before this one's.
+// Called by every thread of the workgroup.
+struct InstanceRef {
+    int sel, first;
+};
+__device__ __forceinline__ InstanceRef find_instance(const int32_t* first, const int32_t* sel, int n, int item,
+                                                     int* slot) {
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        for (int base = 0; base < n; base += kWave) {  // wave-uniform
+            const int c = base + lane;
+            int f0 = 0, f1 = 0, sl = 0;
+            if (c < n) {
+                f0 = first[c];
+                f1 = first[c + 1];
+                sl = sel[c];
+            }
+            const bool hit = c < n && f0 <= item && item < f1;
+            if (__ballot(hit)) {
+                if (hit) {  // exactly one lane: the ranges are disjoint
+                    slot[0] = sl;
+                    slot[1] = f0;
+                }
+                break;
+            }
+        }
     }
-    return lo;
+    __syncthreads();
+    return InstanceRef{__builtin_amdgcn_readfirstlane(slot[0]), __builtin_amdgcn_readfirstlane(slot[1])};
 }
 
 // One stage of many instances in one persistent launch: the grid strides over
@@ -769,16 +801,13 @@ template <int ORDER, int MODE, typename T, int TY, int W>
 __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_batch_kernel(const BatchLaunch L) {
     extern __shared__ double facc_all[];
     __shared__ StageLds<T, TY, W, MODE> lds;
-    using ci32 = const __attribute__((address_space(4))) int32_t*;
+    __shared__ int inst[2];
     const int pos = xcd_contiguous(blockIdx.x, gridDim.x);
     for (int base = 0; base < L.total; base += gridDim.x) {
         const int item = base + pos;
         if (item >= L.total) break;  // workgroup-uniform; later rounds are past the end too
-        const int j = find_instance(L.first, L.n_sel, item);
-        const SArgsPtr a = (SArgsPtr)(L.args + ((ci32)L.sel)[j]);
-        const int local = item - ((ci32)L.first)[j];
-        __syncthreads();  // the previous item's LDS reads are done
-        stage_tile<ORDER, MODE, T, TY, W>(*a, local, facc_all, lds);
+        const InstanceRef r = find_instance(L.first, L.sel, L.n_sel, item, inst);
+        stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)(L.args + r.sel), item - r.first, facc_all, lds);
     }
 }
 

@@ -72,6 +72,8 @@ sn_status check_opts(const sn_batch_opts* o) {
         return fail(SN_ERR_UNSUPPORTED, "launch shape rows_per_wave %d, waves %d not compiled", rows, waves);
     if (o->workgroups_per_cu < -1 || o->workgroups_per_cu > 64)
         return fail(SN_ERR_INVALID, "workgroups_per_cu = %d out of range [-1, 64]", o->workgroups_per_cu);
+    if (o->direct_min_workgroups < -1)
+        return fail(SN_ERR_INVALID, "direct_min_workgroups = %d (>= -1 expected)", o->direct_min_workgroups);
     return SN_OK;
 }
 
@@ -219,13 +221,14 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     const int n_slots = (int)B->slot.size();
     const int lps = B->launches_per_step;
 
-    // Plan the run. The unfinished plans form cache groups: plans whose two
-    // psi buffers fit the cache-group size are packed (slot order) into groups
-    // of at most that many bytes, so that a group's K steps run back to back
-    // out of the 256 MB Infinity Cache; larger plans, which stream from HBM
-    // anyway, form one group whose launches fill the GPU together. Each group
-    // takes its steps in turn; within a group every stage of every member is
-    // one launch (plus one finalize), members dropping out as they finish.
+    // Plan the run. By default all unfinished plans form one group, so that
+    // every stage of all of them is one launch that fills the GPU. With a
+    // cache-group size set, plans whose two psi buffers fit it are packed
+    // (slot order) into groups of at most that many bytes, so that a group's
+    // K steps run back to back out of the 256 MB Infinity Cache; larger plans
+    // form one group. Each group takes its steps in turn; within a group every
+    // stage of every member is one launch (plus one finalize), members
+    // dropping out as they finish.
     std::vector<int64_t> left(n_slots, 0);
     int max_rects = 0;
     std::vector<std::vector<int>> groups;
@@ -233,16 +236,17 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
         std::vector<int> big;
         std::vector<int> cur;
         uint64_t cur_bytes = 0;
-        const uint64_t cap = B->o.cache_group_bytes ? B->o.cache_group_bytes : (uint64_t)64 << 20;
+        const uint64_t cap = B->o.cache_group_bytes;  // 0: no cache groups
         for (int i = 0; i < n_slots; ++i) {
             if (!B->slot[i]) continue;
             left[i] = std::max<int64_t>(0, B->slot[i]->nt - B->slot[i]->step);
             left[i] = std::min<int64_t>(left[i], n_steps);
             if (B->quota[i] > 0) left[i] = std::min<int64_t>(left[i], B->quota[i]);
+            if (B->quota[i] == SN_STEPS_PAUSED) left[i] = 0;
             if (left[i] == 0) continue;
             max_rects = std::max(max_rects, B->slot[i]->n_rects);
             const uint64_t f = 2 * (uint64_t)B->slot[i]->psi_bytes;
-            if (f > cap) {
+            if (cap == 0 || f > cap) {
                 big.push_back(i);
                 continue;
             }
@@ -258,12 +262,20 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
         if (!big.empty()) groups.push_back(big);
     }
     if (groups.empty()) return SN_OK;
+    // Members with at least this many workgroups per stage take their stages
+    // as launches of their own (plain kernel arguments, no instance lookup at
+    // the start of every workgroup); they fill the GPU by themselves.
+    const int64_t direct_min = B->o.direct_min_workgroups < 0
+                                   ? INT64_MAX
+                                   : (B->o.direct_min_workgroups > 0 ? B->o.direct_min_workgroups : 4 * (int64_t)B->cus);
     struct Rec {
         size_t off;  // ints into the run area: sel [n], first [n+1], ffirst [n+1], fsel [n]
         int32_t n, total, ftotal, mode;
+        size_t d_off;  // direct launches: (slot, variant) pairs direct[d_off .. d_off + 2 d_n)
+        int32_t d_n;
     };
     std::vector<Rec> recs;
-    std::vector<int32_t> host;
+    std::vector<int32_t> host, direct;
     int64_t stage_launches = 0;
     try {
         for (const auto& g : groups) {
@@ -271,12 +283,20 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             for (int i : g) steps = std::max(steps, left[i]);
             for (int t = 0; t < steps; ++t) {
                 for (int st = 0; st < lps; ++st) {
-                    Rec r{host.size(), 0, 0, 0, (B->o.stepper == SN_HEUN && st == 1) ? (int32_t)kAverage : (int32_t)kUpdate};
+                    Rec r{host.size(), 0, 0, 0, (B->o.stepper == SN_HEUN && st == 1) ? (int32_t)kAverage : (int32_t)kUpdate,
+                          direct.size(), 0};
                     std::vector<int32_t> sel, first, ffirst, fsel;
                     for (int i : g) {
                         if (left[i] <= t) continue;
                         const sn_plan* P = B->slot[i];
                         const int variant = P->stepper == SN_EULER ? ((P->cur + t) & 1) : st;
+                        if (P->n_wg >= direct_min) {
+                            direct.push_back(i);
+                            direct.push_back(variant);
+                            r.d_n++;
+                            ++stage_launches;
+                            continue;
+                        }
                         sel.push_back(2 * i + variant);
                         fsel.push_back(i);
                         first.push_back(r.total);
@@ -292,7 +312,7 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
                     host.insert(host.end(), ffirst.begin(), ffirst.end());
                     host.insert(host.end(), fsel.begin(), fsel.end());
                     recs.push_back(r);
-                    ++stage_launches;
+                    if (r.n > 0) ++stage_launches;
                 }
             }
         }
@@ -304,6 +324,18 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     auto issue = [&](hipStream_t q) -> sn_status {
         const int32_t* base = reinterpret_cast<const int32_t*>(B->ws + B->off_run);
         for (const Rec& r : recs) {
+            for (int32_t e = 0; e < r.d_n; ++e) {
+                const sn_plan* P = B->slot[direct[r.d_off + 2 * e]];
+                const int variant = direct[r.d_off + 2 * e + 1];
+                const StageArgs sa = P->stepper == SN_HEUN
+                                         ? (variant == 0 ? stage_args(P, P->psi[0], nullptr, P->psi[1])
+                                                         : stage_args(P, P->psi[1], P->psi[0], P->psi[0]))
+                                         : (variant == 0 ? stage_args(P, P->psi[0], nullptr, P->psi[1])
+                                                         : stage_args(P, P->psi[1], nullptr, P->psi[0]));
+                HIP_TRY(launch_stage(P->order, r.mode, P->dtype, P->rows, P->waves, sa, q), "stage launch");
+                HIP_TRY(launch_finalize(finalize_args(P, P->stepper == SN_HEUN ? 1 : 0), q), "finalize launch");
+            }
+            if (r.n == 0) continue;
             const int32_t* d = base + r.off;
             BatchLaunch bl{};
             bl.args = reinterpret_cast<const StageArgs*>(B->ws + B->off_stage);
@@ -338,8 +370,11 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             key.push_back(r.total);
             key.push_back(r.ftotal);
             key.push_back(r.mode);
+            key.push_back((int32_t)r.d_off);
+            key.push_back(r.d_n);
         }
         key.insert(key.end(), host.begin(), host.end());
+        key.insert(key.end(), direct.begin(), direct.end());
     }
     const bool replay = B->o.use_graph && B->graph_exec && B->graph_epoch == B->epoch && key == B->graph_key;
     if (replay) {
@@ -394,8 +429,8 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
 sn_status sn_batch_set_steps(sn_batch* B, int32_t slot, int32_t steps) {
     if (!B) return fail(SN_ERR_INVALID, "batch is NULL");
     if (slot < 0 || slot >= (int)B->slot.size() || !B->slot[slot]) return fail(SN_ERR_INVALID, "slot %d is not admitted", slot);
-    if (steps < 0 || steps > B->o.max_steps_per_run)
-        return fail(SN_ERR_INVALID, "steps = %d out of range [0, %d]", steps, B->o.max_steps_per_run);
+    if (steps < SN_STEPS_PAUSED || steps > B->o.max_steps_per_run)
+        return fail(SN_ERR_INVALID, "steps = %d out of range [%d, %d]", steps, SN_STEPS_PAUSED, B->o.max_steps_per_run);
     B->quota[slot] = steps;
     return SN_OK;
 }

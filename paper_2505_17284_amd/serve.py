@@ -53,17 +53,46 @@ def work_quotas(costs: dict, k: int) -> dict:
     return {key: max(1, min(k, int(round(k * cmin / c)))) for key, c in costs.items()}
 
 
+def arrival_quotas(order: list, costs: dict, k: int, backfill: float = 0.25, min_work: float = 2e9) -> dict:
+    """Steps per run that keep arrival order: the oldest admitted request takes
+    k steps; later ones, oldest first, fill in until the run holds
+    max(k cost(oldest) (1 + backfill), min_work) bytes of psi steps (so that
+    short requests ride along with a long one and many short ones fill the
+    GPU together); a request that no longer fits is paused for the run."""
+    if not order:
+        return {}
+    head = order[0]
+    target = max(k * costs[head] * (1.0 + backfill), min_work)
+    used = 0.0
+    out = {}
+    for key in order:
+        c = costs[key]
+        steps = k if key == head else min(k, int((target - used) // c))
+        if steps <= 0:
+            out[key] = B.PAUSED
+            continue
+        out[key] = steps
+        used += steps * c
+    return out
+
+
 def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_run: int = 32,
-          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "work", verbose: bool = False):
+          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "arrival", verbose: bool = False,
+          batch_factory=None):
     """Continuous batching over `requests` = [(arrival_s, Problem)], Heun + minmod.
 
-    policy "work": per-run step quotas share the GPU by work (short requests
-    are not held to the pace of long ones); "steps": every admitted request
-    takes steps_per_run steps per run. Returns per-request records and totals."""
+    policy "arrival": the oldest admitted request takes full runs and later
+    ones fill in (arrival_quotas), so no request is slowed much by later
+    arrivals; "work": per-run step quotas share the GPU by work (short
+    requests finish fast, long ones are slowed down); "steps": every admitted
+    request takes steps_per_run steps per run. Returns per-request records and
+    totals. batch_factory (default batch.Batch) builds one batch per storage
+    type; the host-only tests pass a stand-in that models the device."""
     dtypes = sorted({p.psi_dtype for _, p in requests})
-    batches = {d: B.Batch(order=2, stepper=I.HEUN, psi_dtype=d, max_instances=max_instances,
-                          steps_per_run=steps_per_run, rows_per_wave=rows_per_wave,
-                          waves_per_group=waves_per_group) for d in dtypes}
+    make = batch_factory or B.Batch
+    batches = {d: make(order=2, stepper=I.HEUN, psi_dtype=d, max_instances=max_instances,
+                       steps_per_run=steps_per_run, rows_per_wave=rows_per_wave,
+                       waves_per_group=waves_per_group) for d in dtypes}
     fps = [B.footprint(p, rows_per_wave, waves_per_group) for _, p in requests]
     for i, f in enumerate(fps):
         if f > hbm_budget_bytes:
@@ -99,9 +128,14 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
                 peak = max(peak, used)
                 rec[i]["admitted"] = time.perf_counter() - t0
                 changed = True
-            if policy == "work" and changed:
+            if policy in ("work", "arrival") and changed:
                 costs = {key: step_cost(requests[i][1]) for key, i in slot_of.items()}
-                for (d, s), q in work_quotas(costs, steps_per_run).items():
+                if policy == "work":
+                    quotas = work_quotas(costs, steps_per_run)
+                else:
+                    order = sorted(slot_of, key=lambda key: slot_of[key])  # request index = arrival order
+                    quotas = arrival_quotas(order, costs, steps_per_run)
+                for (d, s), q in quotas.items():
                     batches[d].set_steps(s, q)
                 changed = False
             active = [b for b in batches.values() if b.unfinished()]
@@ -112,7 +146,8 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
             for b in active:
                 b.run()
             windows += 1
-            _sync()
+            for b in active:
+                b.synchronize()
             for d, b in batches.items():
                 for s in b.done_slots():
                     i = slot_of.pop((d, s))
@@ -235,7 +270,7 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
 
 
 def sweep(n_requests: int = 24, rates=(0.5, 0.9), seed: int = 0, budget_gb: float = 200.0,
-          dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32, policy: str = "work",
+          dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32, policy: str = "arrival",
           verbose: bool = False):
     """Capacity from the one-at-a-time path, then both paths at fractions of it."""
     base = I.serving_requests(n_requests, rate=1.0, seed=seed, dtypes=dtypes)

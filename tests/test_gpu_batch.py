@@ -81,6 +81,42 @@ def test_batch_bit_identical_to_alone(bt, use_graph, window):
         b.close()
 
 
+def test_batch_cache_groups_bit_identical(bt):
+    """Cache groups (small plans packed into groups that take their steps of a
+    run back to back) change only the launch sequence, not any result."""
+    batch, solver = bt
+    probs = _mix()
+    alone = _alone(solver, probs)
+    b = batch.Batch(max_instances=8, steps_per_run=5, cache_group_bytes=1 << 20)
+    try:
+        slots = [b.admit(p) for p in probs]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            _same(b.result(s, psi=True), a, p.name)
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("direct_min", [1, 30])
+@pytest.mark.parametrize("stepper", [I.EULER, I.HEUN])
+def test_batch_direct_launches_bit_identical(bt, direct_min, stepper):
+    """Members at or above direct_min_workgroups take their stages as launches
+    of their own (all members with 1, two of five with 30); results do not change."""
+    batch, solver = bt
+    probs = _mix(stepper=stepper)
+    alone = _alone(solver, probs)
+    b = batch.Batch(stepper=stepper, max_instances=8, steps_per_run=3, direct_min_workgroups=direct_min)
+    try:
+        slots = [b.admit(p) for p in probs]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            _same(b.result(s, psi=True), a, p.name)
+    finally:
+        b.close()
+
+
 @pytest.mark.parametrize("order,stepper", [(1, I.EULER), (2, I.EULER), (1, I.HEUN)])
 def test_batch_other_schemes(bt, order, stepper):
     batch, solver = bt

@@ -218,6 +218,30 @@ def test_full_size_lattice700_random_state(sv, orc):
     assert okp, repp
 
 
+def test_full_size_cavity1300_random_state(sv, orc):
+    """The walled-cavity configuration at full size (1300^2 cells, 512
+    ordinates, minmod, Heun, inflow through the west side; 3.5 GB per psi
+    buffer, far above the 256 MB Infinity Cache) in its default launch shape:
+    one step from a random state, sampled field values, phi and every QoI
+    against the oracle."""
+    p = I.config(3)
+    psi0 = I.random_state(p, 1300, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 1, psi0=psi0)
+    del psi0
+    oi, oint = _orc_dicts(o_)
+    ok, rep = compare_qoi(g_["qoi"], g_["qoi_int"], oi, oint)
+    print(rep)
+    assert ok, rep
+    rng = np.random.Generator(np.random.PCG64(1))
+    idx = tuple(rng.integers(0, s, 50000) for s in o_["psi"].shape)
+    okf, repf = compare_field(g_["psi"][idx], o_["psi"][idx], 2)
+    print("sampled psi:", repf)
+    assert okf, repf
+    okp, repp = compare_field(g_["phi"], o_["phi"], 2)
+    print("phi:", repp)
+    assert okp, repp
+
+
 def test_lattice700_full_run_matches_golden(sv):
     """Full 640-step solve of the benchmark workload against the oracle's QoIs
     stored by tests/golden/make_oracle_goldens.py."""

@@ -1,0 +1,53 @@
+"""Per-QoI error of the stored-psi precisions against the FP64 oracle.
+
+The full lattice benchmark (700^2 cells, 256 ordinates, minmod, Heun, 640
+steps to T = 3.2) is solved with FP32 and with BF16 psi storage (FP32
+arithmetic in both) and every instantaneous and time-integrated QoI is
+compared with the oracle's values stored by tests/golden/make_oracle_goldens.py.
+FP32 is held to the 1e-5 relative target; BF16 rounds every stored value to
+8 significant bits (relative 2^-9), so it is held to 1e-2 and its errors are
+reported, not hidden. Run with -s to see the table.
+"""
+
+import json
+import os
+
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+from tests.parity import compare_qoi
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_lattice700_M256_heun2.json")
+BOUND = {"f32": 1e-5, "bf16": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17284_amd import solver
+
+    return solver
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_lattice700_full_run_error_per_qoi(sv, dtype):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden not generated")
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    p = I.config(2).replace(psi_dtype=dtype)
+    print(f"[case] {p.name} psi {dtype}", flush=True)
+    r = sv.solve(p)
+    print(f"| storage | QoI | oracle (FP64) | GPU | relative error |")
+    for kind, g, o in (("at T", r["qoi"], gold["qoi"]), ("integrated", r["qoi_int"], gold["qoi_int"])):
+        for name, ov in o.items():
+            gv = g[name]
+            rel = abs(gv - ov) / abs(ov) if ov else abs(gv - ov)
+            print(f"| {dtype} | {name} {kind} | {ov:.10g} | {gv:.10g} | {rel:.2e}{'' if ov else ' (abs)'} |")
+    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], rtol=BOUND[dtype])
+    assert ok, rep

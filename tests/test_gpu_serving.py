@@ -26,10 +26,11 @@ def srv():
     return serve
 
 
-def test_serving_results_same_alone_and_in_the_mix(srv):
+@pytest.mark.parametrize("policy", ["arrival", "work", "steps"])
+def test_serving_results_same_alone_and_in_the_mix(srv, policy):
     reqs = I.serving_requests(14, rate=40.0, seed=5, dtypes=("f32", "bf16"), n_range=(40, 80))
-    print("[case] serving 14 requests", flush=True)
-    rec_b, tot_b = srv.serve(reqs, hbm_budget_bytes=int(2e9), max_instances=6, steps_per_run=4)
+    print(f"[case] serving 14 requests, policy {policy}", flush=True)
+    rec_b, tot_b = srv.serve(reqs, hbm_budget_bytes=int(2e9), max_instances=6, steps_per_run=4, policy=policy)
     rec_f, tot_f = srv.serve_fifo(reqs)
     assert srv.same_results(rec_b, rec_f) == 0.0
     for r in rec_b:
