@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--uq", type=int, default=256,
                     help="instances of the batched UQ workload (0 skips it)")
-    ap.add_argument("--serving-requests", type=int, default=16,
+    ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the serving comparison (0 skips it)")
     ap.add_argument("--serving-load", type=float, default=0.9,
                     help="arrival rate as a fraction of the one-at-a-time capacity")
@@ -247,7 +247,7 @@ def main():
     if args.serving_requests:
         print(f"[bench] serving: {args.serving_requests} requests at load {args.serving_load}",
               file=sys.stderr, flush=True)
-        line["serving"] = serve.sweep(args.serving_requests, rates=(args.serving_load,), verbose=True)
+        line["serving"] = serve.sweep(args.serving_requests, rates=(args.serving_load,), verbose=False)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(line), flush=True)

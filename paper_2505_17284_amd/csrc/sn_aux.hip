@@ -160,6 +160,7 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
         a.inst[s] = tot;
         a.integ[s] += a.coef * tot;
         if (!isfinite(tot)) a.flags[0] = 1;
+        if (s == 0) a.counter[0] += 1;  // one finalize per stage; the next stage reads it
     }
 }
 

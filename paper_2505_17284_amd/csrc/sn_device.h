@@ -72,6 +72,7 @@ struct StageArgs {
     const RegConst* reg;
     const uint8_t* region;  // plane of region ids
     double* qpart;          // [nq][n_wg] per-workgroup QoI partial sums
+    const int32_t* counter; // stages finalised so far (seeds BF16 stochastic rounding)
     int64_t plane;          // ny_alloc * pitch (elements)
     int32_t nx, ny, pitch, M;
     int32_t ox;             // column of interior cell 0 in a row
@@ -124,6 +125,7 @@ struct FinalizeArgs {
     double* inst;           // [nq] instantaneous QoIs of the stage input
     double* integ;          // [nq] running time integrals
     int32_t* flags;         // bit 0: a non-finite QoI was seen
+    int32_t* counter;       // stages finalised so far (incremented once per finalize)
     double coef;            // weight of this stage in the time integral
     int32_t n_wg, nq;
 };

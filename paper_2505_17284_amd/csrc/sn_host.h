@@ -99,5 +99,9 @@ namespace snh {
 snk::StageArgs stage_args(const sn_plan* P, const char* in, const char* old, char* out);
 // Finalize arguments of a stage of P; kind 0 Euler, 1/2 Heun stages, -1 QoI only.
 snk::FinalizeArgs finalize_args(const sn_plan* P, int kind);
+// Issue n whole steps of P on s with plain launches (no graph, no timing);
+// advances P's step counter and buffer parity. Used by a batch for plans
+// that fill the GPU on their own.
+sn_status issue_steps(sn_plan* P, int n, hipStream_t s);
 
 }  // namespace snh

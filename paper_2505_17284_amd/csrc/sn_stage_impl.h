@@ -72,7 +72,7 @@ constexpr uint32_t kDropOffset = 0x80000000u;
 template <>
 struct Store<float> {
     static __device__ __forceinline__ float2 load2(const char* p) { return *reinterpret_cast<const float2*>(p); }
-    static __device__ __forceinline__ float2 round2(float2 v) { return v; }
+    static __device__ __forceinline__ float2 round2(float2 v, uint32_t, uint32_t) { return v; }
     static __device__ __forceinline__ void store2(char* p, float2 v) { *reinterpret_cast<float2*>(p) = v; }
     static __device__ __forceinline__ void store1(char* p, float v) { *reinterpret_cast<float*>(p) = v; }
     static __device__ __forceinline__ float2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -96,14 +96,36 @@ __device__ __forceinline__ uint32_t bf16_narrow(float v) {
     return u >> 16;
 }
 
+__device__ __forceinline__ uint32_t bf16_sr(float v, uint32_t r) {
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_narrow(v);  // Inf, NaN
+    return (u + (r & 0xffffu)) >> 16;
+}
+
+// MurmurHash3's 32-bit finalizer (fmix32): a bijective mix of the input bits,
+// used to derive reproducible rounding bits from (stage, ordinate, cell).
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
 template <>
 struct Store<uint16_t> {
     static __device__ __forceinline__ float2 load2(const char* p) {
         const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
         return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
     }
-    static __device__ __forceinline__ float2 round2(float2 v) {
-        return make_float2(bf16_widen(bf16_narrow(v.x)), bf16_widen(bf16_narrow(v.y)));
+    // Stochastic rounding to bfloat16 with the random 16-bit values r0, r1:
+    // adding r to the magnitude bits below the kept 16 and truncating rounds
+    // up with probability equal to the discarded fraction, so the stored value
+    // is unbiased. Round-to-nearest would drop every update smaller than half
+    // a bfloat16 ulp (2^-9 relative) and let slowly changing fluxes stagnate.
+    static __device__ __forceinline__ float2 round2(float2 v, uint32_t r0, uint32_t r1) {
+        return make_float2(bf16_widen(bf16_sr(v.x, r0)), bf16_widen(bf16_sr(v.y, r1)));
     }
     // v must already be representable (round2): narrowing is then exact.
     static __device__ __forceinline__ void store2(char* p, float2 v) {
@@ -205,6 +227,7 @@ struct WaveCtx {
     bool ge_first;       // column nx-1 is the lane's first cell
     bool ghost_wave;     // the wave holds a boundary cell (wave-uniform)
     uint32_t pitchb;     // bytes per padded row
+    uint32_t seed;       // BF16 storage: stages finalised so far (rounding bits), else 0
     uint32_t planeb;     // bytes per plane
     bool ragged;         // some lane of the wave owns only its first cell (wave-uniform)
     bool v0, v1;         // the lane's cells are output cells of this wave
@@ -508,8 +531,14 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
                 v.x = 0.5f * (oldv[t].x + v.x);
                 v.y = 0.5f * (oldv[t].y + v.y);
             }
-            v = Store<T>::round2(v);
             const uint32_t rowb = (uint32_t)(w.y0 + t + kGhost) * w.pitchb;
+            uint32_t r0 = 0, r1 = 0;
+            if (sizeof(T) == 2) {  // rounding bits from (stage, ordinate, cell pair of the plane)
+                const uint32_t sk = fmix32(fmix32(w.seed) + (uint32_t)k);  // wave-uniform
+                r0 = fmix32(sk ^ ((rowb + w.lane_off) / (uint32_t)sizeof(T)));
+                r1 = r0 >> 16;  // the two halves of one mixed word, one per cell
+            }
+            v = Store<T>::round2(v, r0, r1);
             Store<T>::bstore2(rout, w.store_off, rowb, v);  // halo and partial lanes drop the pair
             if (w.ragged) Store<T>::bstore1(rout, w.single_off, rowb, v.x);
             if (w.ghost_wave) write_frame<T, TY, SX, SY>(a, o, k, j, rowb, rout, w, v);
@@ -630,6 +659,7 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
     w.lane_off = (uint32_t)pcc * (uint32_t)sizeof(T);
     w.pitchb = (uint32_t)a.pitch * (uint32_t)sizeof(T);
     w.planeb = (uint32_t)((size_t)a.plane * sizeof(T));
+    w.seed = sizeof(T) == 2 ? (uint32_t)*a.counter : 0u;
     w.v0 = w.i0 < a.nx;
     w.v1 = w.i0 + 1 < a.nx;
     w.store_off = w.v1 ? w.lane_off : kDropOffset;

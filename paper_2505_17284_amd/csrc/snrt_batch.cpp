@@ -262,20 +262,21 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
         if (!big.empty()) groups.push_back(big);
     }
     if (groups.empty()) return SN_OK;
-    // Members with at least this many workgroups per stage take their stages
+    // Members with at least this many workgroups per stage take their steps
     // as launches of their own (plain kernel arguments, no instance lookup at
-    // the start of every workgroup); they fill the GPU by themselves.
+    // the start of every workgroup), all steps of the run of one member back
+    // to back, after the shared launches: they fill the GPU by themselves,
+    // and consecutive stages of one plan reuse what the cache holds of it.
     const int64_t direct_min = B->o.direct_min_workgroups < 0
                                    ? INT64_MAX
                                    : (B->o.direct_min_workgroups > 0 ? B->o.direct_min_workgroups : 4 * (int64_t)B->cus);
     struct Rec {
         size_t off;  // ints into the run area: sel [n], first [n+1], ffirst [n+1], fsel [n]
         int32_t n, total, ftotal, mode;
-        size_t d_off;  // direct launches: (slot, variant) pairs direct[d_off .. d_off + 2 d_n)
-        int32_t d_n;
     };
     std::vector<Rec> recs;
-    std::vector<int32_t> host, direct;
+    std::vector<int32_t> host;
+    std::vector<int> direct;  // slots advanced with launches of their own
     int64_t stage_launches = 0;
     try {
         for (const auto& g : groups) {
@@ -283,18 +284,15 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             for (int i : g) steps = std::max(steps, left[i]);
             for (int t = 0; t < steps; ++t) {
                 for (int st = 0; st < lps; ++st) {
-                    Rec r{host.size(), 0, 0, 0, (B->o.stepper == SN_HEUN && st == 1) ? (int32_t)kAverage : (int32_t)kUpdate,
-                          direct.size(), 0};
+                    Rec r{host.size(), 0, 0, 0, (B->o.stepper == SN_HEUN && st == 1) ? (int32_t)kAverage : (int32_t)kUpdate};
                     std::vector<int32_t> sel, first, ffirst, fsel;
                     for (int i : g) {
                         if (left[i] <= t) continue;
                         const sn_plan* P = B->slot[i];
                         const int variant = P->stepper == SN_EULER ? ((P->cur + t) & 1) : st;
                         if (P->n_wg >= direct_min) {
-                            direct.push_back(i);
-                            direct.push_back(variant);
-                            r.d_n++;
-                            ++stage_launches;
+                            if (t == 0 && st == 0) direct.push_back(i);
+                            stage_launches++;
                             continue;
                         }
                         sel.push_back(2 * i + variant);
@@ -311,8 +309,10 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
                     host.insert(host.end(), first.begin(), first.end());
                     host.insert(host.end(), ffirst.begin(), ffirst.end());
                     host.insert(host.end(), fsel.begin(), fsel.end());
-                    recs.push_back(r);
-                    if (r.n > 0) ++stage_launches;
+                    if (r.n > 0) {
+                        recs.push_back(r);
+                        ++stage_launches;
+                    }
                 }
             }
         }
@@ -324,18 +324,6 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     auto issue = [&](hipStream_t q) -> sn_status {
         const int32_t* base = reinterpret_cast<const int32_t*>(B->ws + B->off_run);
         for (const Rec& r : recs) {
-            for (int32_t e = 0; e < r.d_n; ++e) {
-                const sn_plan* P = B->slot[direct[r.d_off + 2 * e]];
-                const int variant = direct[r.d_off + 2 * e + 1];
-                const StageArgs sa = P->stepper == SN_HEUN
-                                         ? (variant == 0 ? stage_args(P, P->psi[0], nullptr, P->psi[1])
-                                                         : stage_args(P, P->psi[1], P->psi[0], P->psi[0]))
-                                         : (variant == 0 ? stage_args(P, P->psi[0], nullptr, P->psi[1])
-                                                         : stage_args(P, P->psi[1], nullptr, P->psi[0]));
-                HIP_TRY(launch_stage(P->order, r.mode, P->dtype, P->rows, P->waves, sa, q), "stage launch");
-                HIP_TRY(launch_finalize(finalize_args(P, P->stepper == SN_HEUN ? 1 : 0), q), "finalize launch");
-            }
-            if (r.n == 0) continue;
             const int32_t* d = base + r.off;
             BatchLaunch bl{};
             bl.args = reinterpret_cast<const StageArgs*>(B->ws + B->off_stage);
@@ -370,14 +358,13 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             key.push_back(r.total);
             key.push_back(r.ftotal);
             key.push_back(r.mode);
-            key.push_back((int32_t)r.d_off);
-            key.push_back(r.d_n);
         }
         key.insert(key.end(), host.begin(), host.end());
-        key.insert(key.end(), direct.begin(), direct.end());
     }
     const bool replay = B->o.use_graph && B->graph_exec && B->graph_epoch == B->epoch && key == B->graph_key;
-    if (replay) {
+    if (recs.empty()) {
+        // only members with launches of their own this run
+    } else if (replay) {
         HIP_TRY(hipGraphLaunch(B->graph_exec, s), "hipGraphLaunch");
         B->graph_replays++;
     } else {
@@ -416,10 +403,18 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             if (st != SN_OK) return st;
         }
     }
+    // Members with launches of their own: all their steps of the run back to
+    // back, in stream order after the shared launches.
+    std::vector<char> is_direct(n_slots, 0);
+    for (int i : direct) {
+        is_direct[i] = 1;
+        sn_status st = issue_steps(B->slot[i], (int)left[i], s);
+        if (st != SN_OK) return st;
+    }
     B->launches += stage_launches;
     for (int i = 0; i < n_slots; ++i) {
         sn_plan* P = B->slot[i];
-        if (!P) continue;
+        if (!P || is_direct[i]) continue;  // issue_steps advanced the direct members
         P->step += left[i];
         if (P->stepper == SN_EULER) P->cur ^= (int)(left[i] & 1);
     }

@@ -289,6 +289,7 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
     a.reg = P->sp<RegConst>(P->off_reg);
     a.region = P->sp<uint8_t>(P->off_region);
     a.qpart = P->sp<double>(P->off_qpart);
+    a.counter = P->sp<int32_t>(P->off_flags) + 1;
     a.plane = P->plane;
     a.nx = P->nx;
     a.ny = P->ny;
@@ -325,6 +326,7 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.inst = P->sp<double>(P->off_inst);
     f.integ = P->sp<double>(P->off_integ);
     f.flags = P->sp<int32_t>(P->off_flags);
+    f.counter = P->sp<int32_t>(P->off_flags) + 1;
     f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
     f.n_wg = P->n_wg;
     f.nq = P->nq;
@@ -459,6 +461,8 @@ sn_status run_steps(sn_plan* P, int n, hipStream_t s) {
 
 }  // namespace
 
+sn_status snh::issue_steps(sn_plan* P, int n, hipStream_t s) { return launch_steps(P, n, s, false); }
+
 extern "C" {
 
 const char* sn_last_error(void) { return snh::last_error(); }
@@ -557,7 +561,7 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
                            hipMemcpyHostToDevice, s), "upload scales");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_integ), 0, kMaxQ * sizeof(double), s), "clear integrals");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_inst), 0, kMaxQ * sizeof(double), s), "clear QoIs");
-    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_flags), 0, sizeof(int32_t), s), "clear flags");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_flags), 0, 2 * sizeof(int32_t), s), "clear flags and stage counter");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_phi), 0, P->plane * sizeof(float), s), "clear phi");
     HIP_TRY(hipMemsetAsync(P->psi[0], 0, P->psi_bytes, s), "clear psi A");
     HIP_TRY(hipMemsetAsync(P->psi[1], 0, P->psi_bytes, s), "clear psi B");

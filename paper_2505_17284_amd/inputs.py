@@ -320,6 +320,62 @@ def cavity(n: int = 1300, M: int = 512, order: int = 2, stepper: int = HEUN,
 
 
 # --------------------------------------------------------------------------
+# Hohlraum benchmark (Sec. 3.2.1) on D = [-0.65, 0.65]^2. Every edge of the
+# layout lies on a multiple of 0.05, so for n a multiple of 26 the material
+# interfaces are cell faces. Blocks in units of 0.05 (open sets; cells are
+# assigned by their centres, half-open [lo, hi)):
+#   K (black)  (-13, 13) x (-13, -12) and (-13, 13) x (12, 13)
+#   R (red)    (-13, -12) x (-8, 8)   and (12, 13) x (-8, 8)
+#   G (green)  (-4, -3) x (-7, 7), (3, 4) x (-7, 7), (-4, 4) x (-8, -7), (-4, 4) x (7, 8)
+#   B (blue, capsule interior; not defined in the text, read off G) (-3, 3) x (-7, 7)
+#   W (white)  the rest
+# Materials from the table of the Hohlraum figure (sigma_a, sigma_s):
+# W (0, 0.1), B (100, 0), R (5, 95), G (10, 90), K (50, 50). No source, no
+# initial particles, isotropic inflow 1 through x = -0.65 (xi > 0) and
+# x = 0.65 (xi < 0), vacuum elsewhere, T = 2.6.
+# --------------------------------------------------------------------------
+
+HOHLRAUM_REGIONS = ["W", "B", "R", "G", "K"]
+HOHLRAUM_SIGMA_A = [0.0, 100.0, 5.0, 10.0, 50.0]
+HOHLRAUM_SIGMA_S = [0.1, 0.0, 95.0, 90.0, 50.0]
+HOHLRAUM_TALLIES = ["GB", "R", "K", "W"]  # absorption QoI-2 over G u B, R, K; W closes the balance
+HOHLRAUM_REGION_TALLY = [3, 0, 1, 0, 2]
+
+
+def hohlraum_region_map(n: int) -> np.ndarray:
+    """region[j, i] of the Hohlraum layout on an n x n grid (ids of HOHLRAUM_REGIONS)."""
+    c = _cavity_centres_scaled(n)  # n * cell centre in units of 0.05
+
+    def inside(lo, hi):
+        return (c >= lo * n) & (c < hi * n)
+
+    def box(x_lo, x_hi, y_lo, y_hi):
+        return inside(y_lo, y_hi)[:, None] & inside(x_lo, x_hi)[None, :]
+
+    region = np.zeros((n, n), dtype=np.uint8)
+    region[box(-13, 13, -13, -12) | box(-13, 13, 12, 13)] = 4
+    region[box(-13, -12, -8, 8) | box(12, 13, -8, 8)] = 2
+    region[box(-4, -3, -7, 7) | box(3, 4, -7, 7) | box(-4, 4, -8, -7) | box(-4, 4, 7, 8)] = 3
+    region[box(-3, 3, -7, 7)] = 1
+    return region
+
+
+def hohlraum(n: int = 260, M: int = 128, order: int = 2, stepper: int = HEUN, cfl: float = 0.5,
+             t_end: float = 2.6, psi_dtype: str = "f32", quad: Quadrature | None = None,
+             name: str | None = None) -> Problem:
+    quad = quad if quad is not None else quadrature_for(M)
+    return Problem(
+        name=name or f"hohlraum_n{n}_M{quad.M}",
+        nx=n, ny=n, h=1.3 / n, x0=-0.65, y0=-0.65, quad=quad, region=hohlraum_region_map(n),
+        sigma_a=np.array(HOHLRAUM_SIGMA_A), sigma_s=np.array(HOHLRAUM_SIGMA_S), q=np.zeros(5),
+        tally=np.array(HOHLRAUM_REGION_TALLY, dtype=np.uint8), tally_names=list(HOHLRAUM_TALLIES),
+        bc=(BC_INFLOW, BC_INFLOW, BC_VACUUM, BC_VACUUM), inflow=(1.0, 1.0, 0.0, 0.0),
+        order=order, stepper=stepper, cfl=cfl, t_end=t_end, rects=np.array([(0, 0, n, n)], dtype=np.int32),
+        rect_names=["domain"], psi_dtype=psi_dtype, meta={"kind": "hohlraum"},
+    )
+
+
+# --------------------------------------------------------------------------
 # Test problems with closed-form behaviour.
 # --------------------------------------------------------------------------
 

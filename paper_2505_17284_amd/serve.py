@@ -53,15 +53,20 @@ def work_quotas(costs: dict, k: int) -> dict:
     return {key: max(1, min(k, int(round(k * cmin / c)))) for key, c in costs.items()}
 
 
-def arrival_quotas(order: list, costs: dict, k: int, backfill: float = 0.25, min_work: float = 2e9) -> dict:
+def arrival_quotas(order: list, costs: dict, k: int, backfill: float = 0.25, min_work: float = 2e9,
+                   k_max: int | None = None) -> dict:
     """Steps per run that keep arrival order: the oldest admitted request takes
-    k steps; later ones, oldest first, fill in until the run holds
-    max(k cost(oldest) (1 + backfill), min_work) bytes of psi steps (so that
-    short requests ride along with a long one and many short ones fill the
-    GPU together); a request that no longer fits is paused for the run."""
+    k steps (more, up to k_max, while that is less than min_work bytes of psi
+    steps, so that a run is never mostly overhead); later ones, oldest first,
+    fill in until the run holds max(k cost(oldest) (1 + backfill), min_work)
+    bytes of psi steps (so that short requests ride along with a long one and
+    many short ones fill the GPU together); a request that no longer fits is
+    paused for the run."""
     if not order:
         return {}
     head = order[0]
+    if k_max is not None and k_max > k:
+        k = max(k, min(k_max, int(min_work // costs[head])))
     target = max(k * costs[head] * (1.0 + backfill), min_work)
     used = 0.0
     out = {}
@@ -77,21 +82,29 @@ def arrival_quotas(order: list, costs: dict, k: int, backfill: float = 0.25, min
 
 
 def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_run: int = 32,
-          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "arrival", verbose: bool = False,
-          batch_factory=None):
+          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "srpt", verbose: bool = False,
+          batch_factory=None, max_steps_per_run: int = 256, run_work: float = 2e10):
     """Continuous batching over `requests` = [(arrival_s, Problem)], Heun + minmod.
 
-    policy "arrival": the oldest admitted request takes full runs and later
-    ones fill in (arrival_quotas), so no request is slowed much by later
-    arrivals; "work": per-run step quotas share the GPU by work (short
+    policy "srpt": the admitted request with the least remaining work (psi
+    steps x bytes per step) takes full runs and the others fill in by the same
+    rule, so short requests overtake long ones that are already running (the
+    GPU is shared by preemption at run boundaries; each request still runs at
+    the full speed of its own kernels); "arrival": the same with the oldest
+    request first, so no request is slowed much by later arrivals; "work": per-run step quotas share the GPU by work (short
     requests finish fast, long ones are slowed down); "steps": every admitted
-    request takes steps_per_run steps per run. Returns per-request records and
-    totals. batch_factory (default batch.Batch) builds one batch per storage
-    type; the host-only tests pass a stand-in that models the device."""
+    request takes steps_per_run steps per run. With "arrival" a run holds at
+    least run_work bytes of psi steps (up to max_steps_per_run steps of the
+    oldest request), so that runs of short requests are not mostly overhead.
+    Returns per-request records and totals. batch_factory (default
+    batch.Batch) builds one batch per storage type; the host-only tests pass a
+    stand-in that models the device."""
     dtypes = sorted({p.psi_dtype for _, p in requests})
     make = batch_factory or B.Batch
+    k_max = max(steps_per_run, max_steps_per_run if policy in ("arrival", "srpt") else steps_per_run)
+    n_steps = [solver.plan_info(p)["n_steps"] for _, p in requests]
     batches = {d: make(order=2, stepper=I.HEUN, psi_dtype=d, max_instances=max_instances,
-                       steps_per_run=steps_per_run, rows_per_wave=rows_per_wave,
+                       steps_per_run=k_max, rows_per_wave=rows_per_wave,
                        waves_per_group=waves_per_group) for d in dtypes}
     fps = [B.footprint(p, rows_per_wave, waves_per_group) for _, p in requests]
     for i, f in enumerate(fps):
@@ -128,13 +141,20 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
                 peak = max(peak, used)
                 rec[i]["admitted"] = time.perf_counter() - t0
                 changed = True
-            if policy in ("work", "arrival") and changed:
+            if changed:
                 costs = {key: step_cost(requests[i][1]) for key, i in slot_of.items()}
                 if policy == "work":
                     quotas = work_quotas(costs, steps_per_run)
-                else:
+                elif policy == "arrival":
                     order = sorted(slot_of, key=lambda key: slot_of[key])  # request index = arrival order
-                    quotas = arrival_quotas(order, costs, steps_per_run)
+                    quotas = arrival_quotas(order, costs, steps_per_run, min_work=run_work, k_max=k_max)
+                elif policy == "srpt":
+                    rem = {key: costs[key] * (n_steps[i] - batches[key[0]].status(key[1])[1])
+                           for key, i in slot_of.items()}
+                    order = sorted(slot_of, key=lambda key: (rem[key], slot_of[key]))
+                    quotas = arrival_quotas(order, costs, steps_per_run, backfill=0.1, min_work=run_work, k_max=k_max)
+                else:
+                    quotas = {key: steps_per_run for key in costs}
                 for (d, s), q in quotas.items():
                     batches[d].set_steps(s, q)
                 changed = False
@@ -270,28 +290,37 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
 
 
 def sweep(n_requests: int = 24, rates=(0.5, 0.9), seed: int = 0, budget_gb: float = 200.0,
-          dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32, policy: str = "arrival",
-          verbose: bool = False):
-    """Capacity from the one-at-a-time path, then both paths at fractions of it."""
+          dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32,
+          policies=("srpt", "arrival"), capacity_batched: bool = True, verbose: bool = False):
+    """Capacity of both paths (all requests at once), then the one-at-a-time
+    path and the continuous-batching loop (each policy) on the same Poisson
+    arrivals at fractions of the one-at-a-time capacity."""
     base = I.serving_requests(n_requests, rate=1.0, seed=seed, dtypes=dtypes)
     # capacity: back-to-back service times of the plain path (arrivals all at 0)
     cap_reqs = [(0.0, p) for _, p in base]
-    cap_rec, _ = serve_fifo(cap_reqs, verbose=verbose)
+    cap_rec, cap_tot = serve_fifo(cap_reqs, verbose=verbose)
     alone = {r["name"]: r["service"] for r in cap_rec}
     capacity = len(cap_rec) / sum(alone.values())
-    out = dict(capacity_solves_per_s=capacity, mean_service_s=float(np.mean(list(alone.values()))),
-               policy=policy, steps_per_run=steps_per_run, rates=[])
+    out = dict(requests=n_requests, capacity_solves_per_s=capacity,
+               mean_service_s=float(np.mean(list(alone.values()))), policies=list(policies),
+               steps_per_run=steps_per_run, rates=[])
+    if capacity_batched:
+        rec_c, tot_c = serve(cap_reqs, int(budget_gb * 1e9), max_instances=max_instances,
+                             steps_per_run=steps_per_run, policy=policies[0], verbose=verbose)
+        out["capacity_batched_solves_per_s"] = len(rec_c) / tot_c["wall_s"]
+        out["capacity_fifo_solves_per_s"] = len(cap_rec) / cap_tot["wall_s"]
     for f in rates:
         lam = f * capacity
         # same requests, arrival times rescaled to rate lam
         arr = [(t / lam, p) for t, p in base]
-        rec_b, tot_b = serve(arr, int(budget_gb * 1e9), max_instances=max_instances, steps_per_run=steps_per_run,
-                             policy=policy, verbose=verbose)
         rec_f, tot_f = serve_fifo(arr, verbose=verbose)
-        out["rates"].append(dict(load=f, rate_per_s=lam,
-                                 batched=summarize(rec_b, tot_b, alone),
-                                 fifo=summarize(rec_f, tot_f, alone),
-                                 max_rel_diff_batched_vs_fifo=same_results(rec_b, rec_f)))
+        entry = dict(load=f, rate_per_s=lam, fifo=summarize(rec_f, tot_f, alone))
+        for pol in policies:
+            rec_b, tot_b = serve(arr, int(budget_gb * 1e9), max_instances=max_instances,
+                                 steps_per_run=steps_per_run, policy=pol, verbose=verbose)
+            entry[f"batched_{pol}"] = summarize(rec_b, tot_b, alone)
+            entry[f"max_rel_diff_{pol}_vs_fifo"] = same_results(rec_b, rec_f)
+        out["rates"].append(entry)
     return out
 
 

@@ -4,6 +4,7 @@ Calls only the FP64 oracle (oracle/) and the seeded problem generators; no
 value here comes from the HIP path.
 
     python tests/golden/make_oracle_goldens.py lattice700   # ~10 min on 8 cores
+    python tests/golden/make_oracle_goldens.py hohlraum260  # ~2 min on 8 cores
 """
 
 import json
@@ -22,6 +23,7 @@ from paper_2505_17284_amd import inputs as I  # noqa: E402
 CASES = {
     "lattice700": ("oracle_lattice700_M256_heun2.json", lambda: I.config(2)),
     "lattice70": ("oracle_lattice70_M32_euler1.json", lambda: I.config(1)),
+    "hohlraum260": ("oracle_hohlraum260_M256_heun2.json", lambda: I.hohlraum(260, 256)),
 }
 
 

@@ -185,14 +185,15 @@ def test_graph_replay_matches_eager(sv):
 
 @pytest.mark.parametrize("order", [1, 2])
 def test_bf16_storage_error_bounded(sv, orc, order):
-    """BF16 psi storage (round to nearest even, FP32 math): each stored value
-    carries a relative rounding error of at most 2^-9, so after a few stages
-    the field error stays within a few 2^-9 of the local magnitude."""
+    """BF16 psi storage (stochastic rounding on store, FP32 math): each stored
+    value carries a relative rounding error below one bfloat16 ulp, 2^-8 (half
+    that for round-to-nearest, which is biased), so after four stages the
+    field error stays within a few 2^-8 of the local magnitude."""
     p = I.random_materials(130, 37, 5, seed=3, order=order, stepper=I.HEUN, bc=BCS["mixed"][0],
                            inflow=BCS["mixed"][1], M=32, psi_dtype="bf16")
     psi0 = I.random_state(p, 5, "smooth")  # exact in bf16
     g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0)
-    okf, rep = compare_field(g_["psi"], o_["psi"], 4, rtol=4 * 2.0 ** -9, atol_scale=2.0 ** -9)
+    okf, rep = compare_field(g_["psi"], o_["psi"], 4, rtol=4 * 2.0 ** -8, atol_scale=2.0 ** -8)
     print("bf16 psi:", rep)
     assert okf, rep
 
@@ -240,6 +241,33 @@ def test_full_size_cavity1300_random_state(sv, orc):
     okp, repp = compare_field(g_["phi"], o_["phi"], 2)
     print("phi:", repp)
     assert okp, repp
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_hohlraum_random_state_few_steps(sv, orc, order):
+    """The Hohlraum layout (five materials, sigma_t up to 100, inflow through
+    both x sides): every element of psi and phi and every QoI after two Heun
+    steps from a random state."""
+    p = I.hohlraum(130, 32, order=order)
+    psi0 = I.random_state(p, 77, "smooth")
+    g, o = _run_both(sv, orc, p, 2, psi0=psi0)
+    _check(p, g, o, 2)
+
+
+def test_hohlraum260_full_run_matches_golden(sv):
+    """Full Hohlraum solve (260^2 cells, 256 ordinates, minmod, Heun, 1040
+    steps to T = 2.6) against the oracle's QoIs stored by
+    tests/golden/make_oracle_goldens.py."""
+    path = os.path.join(GOLDEN, "oracle_hohlraum260_M256_heun2.json")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    with open(path) as f:
+        gold = json.load(f)
+    p = I.hohlraum(260, 256)
+    r = sv.solve(p)
+    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"])
+    print(rep)
+    assert ok, rep
 
 
 def test_lattice700_full_run_matches_golden(sv):

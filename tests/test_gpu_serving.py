@@ -26,7 +26,7 @@ def srv():
     return serve
 
 
-@pytest.mark.parametrize("policy", ["arrival", "work", "steps"])
+@pytest.mark.parametrize("policy", ["srpt", "arrival", "work", "steps"])
 def test_serving_results_same_alone_and_in_the_mix(srv, policy):
     reqs = I.serving_requests(14, rate=40.0, seed=5, dtypes=("f32", "bf16"), n_range=(40, 80))
     print(f"[case] serving 14 requests, policy {policy}", flush=True)
