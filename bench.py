@@ -140,7 +140,8 @@ def main():
     ap.add_argument("--steps", type=int, default=640)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
-    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--group", type=int, default=0, help="ordinates per workgroup, both stages (0: default)")
+    ap.add_argument("--group-avg", type=int, default=0, help="ordinates per workgroup of the averaging stage")
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
@@ -170,7 +171,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     plan = solver.Plan(problem, group_size=args.group, rows_per_wave=args.rows, waves_per_group=args.waves,
-                       device="cuda:0")
+                       device="cuda:0", group_size_average=args.group_avg)
     info = plan.info
     print(f"[bench] plan: {info}", file=sys.stderr, flush=True)
     plan.run(args.warmup, unbounded=True)
@@ -195,7 +196,7 @@ def main():
     stage1_gbs = algorithmic_bytes(problem, info, 1) / (stage1_ms * 1e-3) / 1e9
     step_bytes = algorithmic_bytes(problem, info, 1) + algorithmic_bytes(problem, info, 2)
     traffic = None
-    default_shape = not (args.group or args.rows or args.waves)
+    default_shape = not (args.group or args.group_avg or args.rows or args.waves)
     if default_shape:
         traffic = measured_traffic(args.dtype)
     line = {
@@ -214,7 +215,8 @@ def main():
         "config": {"workload": "lattice700_M256_heun2", "nx": problem.nx, "ny": problem.ny,
                    "ordinates": problem.M, "order": problem.order, "stepper": "heun",
                    "cfl": problem.cfl, "psi_storage": args.dtype,
-                   "group_size": info["group_size"], "rows_per_wave": info["rows_per_wave"],
+                   "group_size": info["group_size"], "group_size_average": info["group_size_average"],
+                   "rows_per_wave": info["rows_per_wave"],
                    "waves_per_group": info["waves_per_group"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -117,8 +117,9 @@ typedef struct sn_plan_info {
     int32_t n_steps;   /* N_t */
     double dt;
     int32_t nx, ny, M, pitch;
-    int32_t n_groups;  /* ordinate groups (phi partials per cell) */
-    int32_t group_size;      /* ordinates per workgroup */
+    int32_t n_groups;  /* ordinate groups of the update stage (Euler, Heun
+                        * stage 1): phi partials per cell it writes */
+    int32_t group_size;      /* ordinates per workgroup of the update stage */
     int32_t rows_per_wave;   /* grid rows per wavefront */
     int32_t waves_per_group; /* wavefronts per workgroup, stacked along y */
     int32_t n_workgroups;    /* workgroups of one stage launch */
@@ -126,6 +127,9 @@ typedef struct sn_plan_info {
     uint64_t scratch_bytes;
     int32_t psi_dtype;
     int32_t step;      /* steps taken so far */
+    int32_t n_groups_average;     /* the same for Heun's averaging stage */
+    int32_t group_size_average;
+    int32_t n_workgroups_average;
 } sn_plan_info;
 
 /* QoIs of the current state (instantaneous) and their time integrals over
@@ -158,13 +162,20 @@ typedef struct sn_plan sn_plan;
 sn_status sn_plan_create(const sn_problem *problem, sn_plan **out);
 
 /* Same, with an explicit launch shape (0 = library default for each):
- * group_size ordinates per workgroup, rows_per_wave grid rows per wavefront
- * (2 or 4), waves_per_group compute wavefronts per workgroup (4 or 8; one
- * more wavefront stages rows for them). Returns
+ * group_size ordinates per workgroup (both stages), rows_per_wave grid rows
+ * per wavefront (2 or 4), waves_per_group compute wavefronts per workgroup
+ * (4 or 8; one more wavefront stages rows for them). Returns
  * SN_ERR_UNSUPPORTED for a shape the library was not compiled for. */
 sn_status sn_plan_create_tuned(const sn_problem *problem, int32_t group_size,
                                int32_t rows_per_wave, int32_t waves_per_group,
                                sn_plan **out);
+
+/* Same, with separate ordinates per workgroup for the update stage (Euler,
+ * Heun stage 1, and the QoI pass) and for Heun's averaging stage, whose
+ * workgroups stream psi^n as well (0 = library default for each). */
+sn_status sn_plan_create_shaped(const sn_problem *problem, int32_t group_size_update,
+                                int32_t group_size_average, int32_t rows_per_wave,
+                                int32_t waves_per_group, sn_plan **out);
 
 sn_status sn_plan_get_info(const sn_plan *plan, sn_plan_info *out);
 

@@ -29,7 +29,7 @@ MAX_RECTS = 4
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = [
-    "sn_plan_create", "sn_plan_create_tuned", "sn_plan_get_info", "sn_plan_bind",
+    "sn_plan_create", "sn_plan_create_tuned", "sn_plan_create_shaped", "sn_plan_get_info", "sn_plan_bind",
     "sn_plan_init", "sn_plan_run", "sn_plan_run_unbounded", "sn_plan_qoi",
     "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_use_graph", "sn_plan_set_timing",
     "sn_plan_kernel_ms", "sn_plan_destroy", "sn_status_str", "sn_last_error",
@@ -59,7 +59,8 @@ class SnPlanInfo(ctypes.Structure):
         ("n_groups", _i32), ("group_size", _i32), ("rows_per_wave", _i32), ("waves_per_group", _i32),
         ("n_workgroups", _i32),
         ("psi_bytes", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64), ("psi_dtype", _i32),
-        ("step", _i32),
+        ("step", _i32), ("n_groups_average", _i32), ("group_size_average", _i32),
+        ("n_workgroups_average", _i32),
     ]
 
 
@@ -114,6 +115,7 @@ def lib():
         PP = ctypes.POINTER(_vp)
         L.sn_plan_create.argtypes = [ctypes.POINTER(SnProblem), PP]
         L.sn_plan_create_tuned.argtypes = [ctypes.POINTER(SnProblem), _i32, _i32, _i32, PP]
+        L.sn_plan_create_shaped.argtypes = [ctypes.POINTER(SnProblem), _i32, _i32, _i32, _i32, PP]
         L.sn_plan_get_info.argtypes = [_vp, ctypes.POINTER(SnPlanInfo)]
         L.sn_plan_bind.argtypes = [_vp, _vp, _vp, _vp]
         L.sn_plan_init.argtypes = [_vp, _vp, _vp]

@@ -53,8 +53,12 @@ struct sn_plan {
     double dt = 0;
     int pitch = 0, ny_alloc = 0, ox = 2;
     int64_t plane = 0, origin = 0;
-    int G = 1, Mg = 1, rows = 2, waves = 4;
-    int ntx = 0, nty = 0, n_wg = 0, nq = 0;
+    // Ordinate groups per stage layout: [0] update stage (Euler, Heun stage 1,
+    // QoI pass), [1] Heun's averaging stage. Buffers hold the larger of each.
+    int G_l[2] = {1, 1}, Mg_l[2] = {1, 1}, n_wg_l[2] = {0, 0};
+    int G = 1, n_wg = 0;  // maxima over the layouts (buffer sizes)
+    int rows = 2, waves = 4;
+    int ntx = 0, nty = 0, nq = 0;
     size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
     size_t off_phi = 0, off_phi_part = 0, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
            off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
@@ -95,7 +99,8 @@ struct sn_plan {
 namespace snh {
 
 // Kernel arguments of one stage of plan P (see launch_stage_pair in
-// snrt_plan.cpp for the buffer roles of each kind).
+// snrt_plan.cpp for the buffer roles of each kind). A stage with psi^n
+// (old != NULL) is Heun's averaging stage and takes that stage's layout.
 snk::StageArgs stage_args(const sn_plan* P, const char* in, const char* old, char* out);
 // Finalize arguments of a stage of P; kind 0 Euler, 1/2 Heun stages, -1 QoI only.
 snk::FinalizeArgs finalize_args(const sn_plan* P, int kind);

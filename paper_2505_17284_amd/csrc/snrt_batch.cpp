@@ -6,7 +6,7 @@
 // Device tables (in the caller's workspace):
 //   stage   [max_instances][2] StageArgs: Heun stage 1 / stage 2, or Euler
 //                                         from buffer A / from buffer B
-//   final   [max_instances]    FinalizeArgs
+//   final   [max_instances][2] FinalizeArgs of the same two stages
 //   run     launch records (stage sel, stage first, finalize first,
 //           finalize sel) of every launch of one run
 // A run of K steps is planned entirely on the host: which plans are still
@@ -89,7 +89,7 @@ void layout(const sn_batch_opts* o, size_t* off_stage, size_t* off_final, size_t
     *off_stage = off;
     off += align256(2 * n * sizeof(StageArgs));
     *off_final = off;
-    off += align256(n * sizeof(FinalizeArgs));
+    off += align256(2 * n * sizeof(FinalizeArgs));
     *off_run = off;
     *run_ints = (size_t)o->max_steps_per_run * lps * (6 * n + 2);
     off += align256(*run_ints * sizeof(int32_t));
@@ -200,10 +200,12 @@ sn_status sn_batch_admit(sn_batch* B, sn_plan* P, int32_t* slot) {
         sa[0] = stage_args(P, P->psi[0], nullptr, P->psi[1]);
         sa[1] = stage_args(P, P->psi[1], nullptr, P->psi[0]);
     }
-    const FinalizeArgs fa = finalize_args(P, P->stepper == SN_HEUN ? 1 : 0);
+    FinalizeArgs fa[2];
+    fa[0] = finalize_args(P, P->stepper == SN_HEUN ? 1 : 0);
+    fa[1] = finalize_args(P, P->stepper == SN_HEUN ? 2 : 0);
     HIP_TRY(hipMemcpy(B->ws + B->off_stage + (size_t)s * 2 * sizeof(StageArgs), sa, sizeof sa, hipMemcpyHostToDevice),
             "upload stage arguments");
-    HIP_TRY(hipMemcpy(B->ws + B->off_final + (size_t)s * sizeof(FinalizeArgs), &fa, sizeof fa, hipMemcpyHostToDevice),
+    HIP_TRY(hipMemcpy(B->ws + B->off_final + (size_t)s * 2 * sizeof(FinalizeArgs), fa, sizeof fa, hipMemcpyHostToDevice),
             "upload finalize arguments");
     B->slot[s] = P;
     P->batch = B;
@@ -290,16 +292,18 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
                         if (left[i] <= t) continue;
                         const sn_plan* P = B->slot[i];
                         const int variant = P->stepper == SN_EULER ? ((P->cur + t) & 1) : st;
-                        if (P->n_wg >= direct_min) {
+                        if (P->n_wg_l[0] >= direct_min) {
                             if (t == 0 && st == 0) direct.push_back(i);
                             stage_launches++;
                             continue;
                         }
+                        // the averaging stage has a layout (groups, workgroups) of its own
+                        const int layout = (P->stepper == SN_HEUN && st == 1) ? 1 : 0;
                         sel.push_back(2 * i + variant);
-                        fsel.push_back(i);
+                        fsel.push_back(2 * i + layout);
                         first.push_back(r.total);
                         ffirst.push_back(r.ftotal);
-                        r.total += P->n_wg;
+                        r.total += P->n_wg_l[layout];
                         r.ftotal += P->nq + (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
                     }
                     r.n = (int32_t)sel.size();

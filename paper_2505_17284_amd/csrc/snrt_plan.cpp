@@ -158,38 +158,49 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     return SN_OK;
 }
 
-void default_shape(const sn_plan* P, int* group_size, int* rows, int* waves) {
+void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* rows, int* waves) {
     // Two rows per wave keep the staged windows, the per-cell constants and the
     // reconstructions within ~80 VGPRs. Four waves per workgroup: taller
     // workgroups stage fewer halo rows but measured slower on the 700 x 700
-    // lattice, the halo rows mostly hitting L2 anyway. Ordinate groups:
-    // split until the launch holds ~4 K workgroups (16 per CU), keeping at
-    // least 8 ordinates per group so the per-workgroup set-up and the group's
-    // phi partial stay small.
+    // lattice. Ordinate groups: at least 8 (one per XCD, so that the tiles an
+    // XCD holds at a time are neighbours that share their halo lines in its
+    // L2), and more until the launch holds ~4 K workgroups (16 per CU),
+    // keeping at least 8 ordinates per group so the per-workgroup set-up and
+    // the group's phi partial stay small.
     *rows = 2;
     *waves = 4;
     const int wg_rows = *waves * *rows;
     const long tiles = (long)((P->nx + kTileX - 1) / kTileX) * ((P->ny + wg_rows - 1) / wg_rows);
     int g = 1;
-    while (tiles * g < 4096 && (P->M + 2 * g - 1) / (2 * g) >= 8) g *= 2;
+    while ((tiles * g < 4096 || g < 8) && (P->M + 2 * g - 1) / (2 * g) >= 8) g *= 2;
     *group_size = (P->M + g - 1) / g;
+    // Heun's averaging stage also streams psi^n; with FP32 storage its LDS
+    // slots are twice those of the update stage, and twice the groups (half
+    // the ordinates each, while that leaves at least 16) measured faster: 356
+    // vs 372 us per launch on the 700 x 700 x 256 lattice, 2.38 vs 2.62 ms on
+    // the 1300 x 1300 x 512 cavity. With BF16 storage the halving measured
+    // slower (368 vs 330 us on the lattice).
+    *group_size_avg = (*group_size >= 32 && P->dtype == SN_F32) ? (*group_size + 1) / 2 : *group_size;
 }
 
-sn_status derive(sn_plan* P, int group_size, int rows, int waves) {
+sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int waves) {
     // dt = CFL * h (Sec. 5.1.3), adjusted so that N_t dt = T (Sec. 4.3).
     const double r = P->t_end / (P->cfl * P->h);
     P->nt = std::max(1, (int)std::ceil(r - 1e-9));
     P->dt = P->t_end / P->nt;
 
-    int gs = 0, rw = 0, wv = 0;
-    default_shape(P, &gs, &rw, &wv);
+    int gs = 0, gsa = 0, rw = 0, wv = 0;
+    default_shape(P, &gs, &gsa, &rw, &wv);
     if (group_size > 0) gs = std::min(group_size, P->M);
+    if (group_size_avg > 0) gsa = std::min(group_size_avg, P->M);
     if (rows > 0) rw = rows;
     if (waves > 0) wv = waves;
     if (!supported_shape(rw, wv))
         return fail(SN_ERR_UNSUPPORTED, "launch shape rows_per_wave %d, waves %d not compiled", rw, wv);
-    P->Mg = gs;
-    P->G = (P->M + gs - 1) / gs;
+    P->Mg_l[0] = gs;
+    P->Mg_l[1] = gsa;
+    for (int l = 0; l < 2; ++l) P->G_l[l] = (P->M + P->Mg_l[l] - 1) / P->Mg_l[l];
+    P->G = std::max(P->G_l[0], P->G_l[1]);
     P->rows = rw;
     P->waves = wv;
     P->elem = P->dtype == SN_F32 ? 4 : 2;
@@ -210,6 +221,7 @@ sn_status derive(sn_plan* P, int group_size, int rows, int waves) {
     const int64_t n_wg = (int64_t)P->ntx * P->nty * P->G;
     if (n_wg > (int64_t)0x7fffffff) return fail(SN_ERR_UNSUPPORTED, "too many workgroups");
     P->n_wg = (int)n_wg;
+    for (int l = 0; l < 2; ++l) P->n_wg_l[l] = P->ntx * P->nty * P->G_l[l];
     P->nq = 1 + P->n_tallies + 2 * P->n_rects;
 
     P->psi_bytes = align256((size_t)P->M * (size_t)P->plane * P->elem);
@@ -279,6 +291,7 @@ sn_status derive(sn_plan* P, int group_size, int rows, int waves) {
 }  // namespace
 
 StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, char* out) {
+    const int l = old ? 1 : 0;  // only the averaging stage reads psi^n
     StageArgs a{};
     a.psi_in = in;
     a.psi_old = old;
@@ -296,11 +309,11 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
     a.pitch = P->pitch;
     a.M = P->M;
     a.ox = P->ox;
-    a.G = P->G;
-    a.Mg = P->Mg;
+    a.G = P->G_l[l];
+    a.Mg = P->Mg_l[l];
     a.ntx = P->ntx;
     a.nty = P->nty;
-    a.n_wg = P->n_wg;
+    a.n_wg = P->n_wg_l[l];
     a.n_tallies = P->n_tallies;
     a.n_rects = P->n_rects;
     a.nq = P->nq;
@@ -311,6 +324,7 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
 }
 
 FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
+    const int l = kind == 2 ? 1 : 0;  // layout of the stage just run
     FinalizeArgs f{};
     f.phi_part = P->sp<float>(P->off_phi_part);
     f.phi = P->sp<float>(P->off_phi);
@@ -318,7 +332,7 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.nx = P->nx;
     f.ny = P->ny;
     f.pitch = P->pitch;
-    f.G = P->G;
+    f.G = P->G_l[l];
     f.ox = P->ox;
     f.n_phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
     f.qpart = P->sp<double>(P->off_qpart);
@@ -328,7 +342,7 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.flags = P->sp<int32_t>(P->off_flags);
     f.counter = P->sp<int32_t>(P->off_flags) + 1;
     f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
-    f.n_wg = P->n_wg;
+    f.n_wg = P->n_wg_l[l];
     f.nq = P->nq;
     return f;
 }
@@ -481,18 +495,18 @@ const char* sn_status_str(sn_status s) {
     }
 }
 
-sn_status sn_plan_create_tuned(const sn_problem* problem, int32_t group_size, int32_t rows_per_wave,
-                               int32_t waves_per_group, sn_plan** out) {
+sn_status sn_plan_create_shaped(const sn_problem* problem, int32_t group_size, int32_t group_size_avg,
+                                int32_t rows_per_wave, int32_t waves_per_group, sn_plan** out) {
     if (!out) return fail(SN_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (group_size < 0 || rows_per_wave < 0 || waves_per_group < 0)
+    if (group_size < 0 || group_size_avg < 0 || rows_per_wave < 0 || waves_per_group < 0)
         return fail(SN_ERR_INVALID, "negative launch shape");
     sn_plan* P = new (std::nothrow) sn_plan();
     if (!P) return fail(SN_ERR_OOM, "plan allocation failed");
     sn_status st;
     try {
         st = validate_and_copy(problem, P);
-        if (st == SN_OK) st = derive(P, group_size, rows_per_wave, waves_per_group);
+        if (st == SN_OK) st = derive(P, group_size, group_size_avg, rows_per_wave, waves_per_group);
     } catch (const std::bad_alloc&) {
         st = fail(SN_ERR_OOM, "host allocation failed");
     }
@@ -504,8 +518,13 @@ sn_status sn_plan_create_tuned(const sn_problem* problem, int32_t group_size, in
     return SN_OK;
 }
 
+sn_status sn_plan_create_tuned(const sn_problem* problem, int32_t group_size, int32_t rows_per_wave,
+                               int32_t waves_per_group, sn_plan** out) {
+    return sn_plan_create_shaped(problem, group_size, group_size, rows_per_wave, waves_per_group, out);
+}
+
 sn_status sn_plan_create(const sn_problem* problem, sn_plan** out) {
-    return sn_plan_create_tuned(problem, 0, 0, 0, out);
+    return sn_plan_create_shaped(problem, 0, 0, 0, 0, out);
 }
 
 sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
@@ -516,11 +535,14 @@ sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
     out->ny = P->ny;
     out->M = P->M;
     out->pitch = P->pitch;
-    out->n_groups = P->G;
-    out->group_size = P->Mg;
+    out->n_groups = P->G_l[0];
+    out->group_size = P->Mg_l[0];
     out->rows_per_wave = P->rows;
     out->waves_per_group = P->waves;
-    out->n_workgroups = P->n_wg;
+    out->n_workgroups = P->n_wg_l[0];
+    out->n_groups_average = P->G_l[1];
+    out->group_size_average = P->Mg_l[1];
+    out->n_workgroups_average = P->n_wg_l[1];
     out->psi_bytes = P->psi_bytes;
     out->scratch_bytes = P->scratch_bytes;
     out->psi_dtype = P->dtype;

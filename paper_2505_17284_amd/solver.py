@@ -25,12 +25,14 @@ def _torch():
     return torch
 
 
-def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0) -> dict:
-    """Derived constants and buffer sizes of a plan (host only, no GPU)."""
+def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
+              group_size_average: int = 0) -> dict:
+    """Derived constants and buffer sizes of a plan (host only, no GPU).
+    group_size applies to both stages unless group_size_average is given."""
     m = MarshalledProblem(problem)
     h = ctypes.c_void_p()
-    check(lib().sn_plan_create_tuned(ctypes.byref(m.struct), group_size, rows_per_wave, waves_per_group,
-                                     ctypes.byref(h)), "sn_plan_create")
+    check(lib().sn_plan_create_shaped(ctypes.byref(m.struct), group_size, group_size_average or group_size,
+                                      rows_per_wave, waves_per_group, ctypes.byref(h)), "sn_plan_create")
     try:
         info = SnPlanInfo()
         check(lib().sn_plan_get_info(h, ctypes.byref(info)), "sn_plan_get_info")
@@ -59,15 +61,16 @@ class Plan:
     """A bound, initialised solve on one GPU."""
 
     def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
-                 device: str = "cuda:0", psi0=None, graph_steps: int = 0):
+                 device: str = "cuda:0", psi0=None, graph_steps: int = 0, group_size_average: int = 0):
         torch = _torch()
         assert problem.n_tallies <= MAX_TALLIES and problem.n_rects <= MAX_RECTS
         self.problem = problem
         self.device = torch.device(device)
         self._m = MarshalledProblem(problem)
         self.h = ctypes.c_void_p()
-        check(lib().sn_plan_create_tuned(ctypes.byref(self._m.struct), group_size, rows_per_wave,
-                                         waves_per_group, ctypes.byref(self.h)), "sn_plan_create")
+        check(lib().sn_plan_create_shaped(ctypes.byref(self._m.struct), group_size,
+                                          group_size_average or group_size, rows_per_wave,
+                                          waves_per_group, ctypes.byref(self.h)), "sn_plan_create")
         info = SnPlanInfo()
         check(lib().sn_plan_get_info(self.h, ctypes.byref(info)), "sn_plan_get_info")
         self.info = {f: getattr(info, f) for f, _ in SnPlanInfo._fields_}
