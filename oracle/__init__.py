@@ -73,7 +73,7 @@ def _load():
         lib.orc_qoi_len.argtypes = [P]
         lib.orc_qoi_len.restype = ctypes.c_int
         lib.orc_qoi.argtypes = [P, d, d, d]
-        lib.orc_advance.argtypes = [P, ctypes.c_int, d, d]
+        lib.orc_advance.argtypes = [P, ctypes.c_int, d, d, d]
         lib.orc_advance.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -180,31 +180,45 @@ def qoi(p, psi):
     return qv
 
 
-def advance(p, psi, n_steps, qint=None):
-    """Advance a copy of ``psi`` by ``n_steps``; returns (psi, qint)."""
+def advance(p, psi, n_steps, qint=None, fluence=None):
+    """Advance a copy of ``psi`` by ``n_steps``; returns (psi, qint).
+
+    With ``fluence`` (an [ny][nx] array, updated in place) the time integral
+    of phi over the steps is added to it with the stepper's rule.
+    """
     m = _Marshalled(p)
     a = _state(m, psi).copy()
     L = _load().orc_qoi_len(m.ref)
     qi = np.zeros(L) if qint is None else np.array(qint, dtype=np.float64)
-    rc = _load().orc_advance(m.ref, int(n_steps), a.ctypes.data, qi.ctypes.data)
+    fl = None
+    if fluence is not None:
+        if fluence.shape != (m.ny, m.nx) or fluence.dtype != np.float64 or not fluence.flags.c_contiguous:
+            raise ValueError("fluence must be a C-contiguous float64 [ny][nx] array")
+        fl = fluence.ctypes.data
+    rc = _load().orc_advance(m.ref, int(n_steps), a.ctypes.data, qi.ctypes.data, fl)
     if rc != 0:
         raise MemoryError("oracle could not allocate its work arrays")
     return a, qi
 
 
-def solve(p, steps=None, psi0=None):
+def solve(p, steps=None, psi0=None, fluence=False):
     """Run the problem from psi0 (default 0) for ``steps`` (default N_t) steps.
 
     Returns a dict: psi, phi, nt, dt, steps, t, qoi (instantaneous at the end),
-    qoi_int (time integrals), names, seconds.
+    qoi_int (time integrals), names, seconds, and with ``fluence`` the time
+    integral of phi per cell ("fluence", [ny][nx]).
     """
     nt, dt = num_steps(p)
     steps = nt if steps is None else int(steps)
     if psi0 is None:
         psi0 = np.zeros((p.quad.M, p.ny, p.nx))
+    fl = np.zeros((p.ny, p.nx)) if fluence else None
     t0 = time.perf_counter()
-    psi, qint = advance(p, psi0, steps)
+    psi, qint = advance(p, psi0, steps, fluence=fl)
     secs = time.perf_counter() - t0
-    return dict(psi=psi, phi=scalar_flux(p, psi), nt=nt, dt=dt, steps=steps,
-                t=steps * dt, qoi=qoi(p, psi), qoi_int=qint, names=qoi_names(p),
-                seconds=secs)
+    out = dict(psi=psi, phi=scalar_flux(p, psi), nt=nt, dt=dt, steps=steps,
+               t=steps * dt, qoi=qoi(p, psi), qoi_int=qint, names=qoi_names(p),
+               seconds=secs)
+    if fluence:
+        out["fluence"] = fl
+    return out

@@ -266,8 +266,18 @@ void orc_qoi(const orc_problem *P, const double *psi, const double *phi, double 
  *   Heun:  psi1 = psi + dt F(psi); psi2 = psi1 + dt F(psi1); psi <- (psi + psi2) / 2.
  * qint accumulates the time integral of the QoI vector with the rule that
  * matches the stepper: Euler dt q(psi^n); Heun dt/2 (q(psi^n) + q(psi1)).
+ * fluence (NULL to skip) accumulates the time integral of phi per cell,
+ * [ny][nx], with the same rule; the Hohlraum QoI-3 to QoI-6 (Sec. 3.2.1)
+ * integrate sigma_a times it over blocks and a line.
  * Returns 0, or -1 if memory could not be allocated. */
-int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint)
+static void add_fluence(const orc_problem *P, double coef, const double *phi, double *fluence)
+{
+    size_t c, ncell = (size_t)P->nx * P->ny;
+    if (!fluence) return;
+    for (c = 0; c < ncell; ++c) fluence[c] += coef * phi[c];
+}
+
+int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint, double *fluence)
 {
     size_t n = (size_t)P->M * P->nx * P->ny;
     size_t ncell = (size_t)P->nx * P->ny;
@@ -290,16 +300,19 @@ int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint)
         orc_rhs(P, psi, phi, F);
         if (P->stepper == 0) {
             for (t = 0; t < L; ++t) qint[t] += dt * qv[t];
+            add_fluence(P, dt, phi, fluence);
 #pragma omp parallel for
             for (e = 0; e < (long long)n; ++e) psi[e] = psi[e] + dt * F[e];
         } else {
             for (t = 0; t < L; ++t) qint[t] += 0.5 * dt * qv[t];
+            add_fluence(P, 0.5 * dt, phi, fluence);
 #pragma omp parallel for
             for (e = 0; e < (long long)n; ++e) psi1[e] = psi[e] + dt * F[e];
             orc_scalar_flux(P, psi1, phi);
             orc_qoi(P, psi1, phi, qv);
             orc_rhs(P, psi1, phi, F);
             for (t = 0; t < L; ++t) qint[t] += 0.5 * dt * qv[t];
+            add_fluence(P, 0.5 * dt, phi, fluence);
 #pragma omp parallel for
             for (e = 0; e < (long long)n; ++e) {
                 double psi2 = psi1[e] + dt * F[e];

@@ -1,0 +1,153 @@
+"""Pins of the oracle's fluence and of its Hohlraum QoI-3 to QoI-6 (Sec. 3.2.1).
+
+The fluence Phi = int_0^T phi dt is pinned by a closed form (the homogeneous
+medium under forward Euler, where phi obeys a scalar linear recurrence) and by
+the time integrals of the QoIs that the oracle already tracks: the absorption
+tallies and the mass are linear functionals of phi, so their integrals must
+equal the same functionals of Phi. The QoI functionals are pinned by fields
+whose block means and line integrals have closed forms (constant, linear in
+x, a single cell) and by the green band of the layout generator.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+
+GREEN = I.HOHLRAUM_REGIONS.index("G")
+
+
+@pytest.fixture(scope="module")
+def hq():
+    from oracle import hohlraum_qoi
+    return hohlraum_qoi
+
+
+def _uniform_green(n, sigma=10.0):
+    """The Hohlraum grid with every cell green (sigma_a uniform)."""
+    p = I.hohlraum(n=n, M=32, order=1, stepper=I.EULER)
+    return p.replace(region=np.full((n, n), GREEN, np.uint8),
+                     sigma_a=np.array([0.0, 0.0, 0.0, sigma, 0.0]))
+
+
+def _centres(p):
+    return p.x0 + (np.arange(p.nx) + 0.5) * p.h, p.y0 + (np.arange(p.ny) + 0.5) * p.h
+
+
+def test_homogeneous_euler_fluence_closed_form(orc):
+    # Reflective walls: phi is uniform and, summing the update over the
+    # ordinates (sum w = 2 pi, scattering conserves), follows
+    # phi^{n+1} = (1 - dt sigma_a) phi^n + 2 pi q dt with phi^0 = 0, so
+    # Phi_N = dt sum_{n<N} phi^n = (2 pi q / sigma_a) (N dt - (1 - r^N) / sigma_a).
+    p = I.homogeneous(nx=5, ny=4, sigma_a=0.7, sigma_s=0.4, q=1.3)
+    nt, dt = orc.num_steps(p)
+    fl = np.zeros((p.ny, p.nx))
+    orc.advance(p, np.zeros((p.quad.M, p.ny, p.nx)), nt, fluence=fl)
+    r = 1.0 - dt * 0.7
+    want = (2 * math.pi * 1.3 / 0.7) * (nt * dt - (1.0 - r ** nt) / 0.7)
+    np.testing.assert_allclose(fl, want, rtol=1e-12)
+
+
+@pytest.mark.parametrize("stepper", [I.EULER, I.HEUN])
+@pytest.mark.parametrize("order", [1, 2])
+def test_fluence_matches_integrated_absorption_and_mass(orc, order, stepper):
+    p = I.random_materials(13, 11, 4, seed=3, order=order, stepper=stepper)
+    psi0 = I.random_state(p, seed=5)
+    fl = np.zeros((p.ny, p.nx))
+    _, qint = orc.advance(p, psi0, 9, fluence=fl)
+    names = orc.qoi_names(p)
+    h2 = p.h * p.h
+    assert qint[names.index("mass")] == pytest.approx(h2 * fl.sum(), rel=1e-12)
+    a = np.asarray(p.sigma_a)[p.region] * fl * h2
+    tally = np.asarray(p.tally)[p.region]
+    for t, tn in enumerate(p.tally_names):
+        assert qint[names.index(f"abs:{tn}")] == pytest.approx(a[tally == t].sum(), rel=1e-12, abs=1e-300)
+
+
+def test_fluence_accumulates_across_calls(orc):
+    p = I.random_materials(9, 7, 3, seed=1, order=2, stepper=I.HEUN)
+    psi0 = I.random_state(p, seed=2)
+    f1 = np.zeros((p.ny, p.nx))
+    orc.advance(p, psi0, 6, fluence=f1)
+    f2 = np.zeros((p.ny, p.nx))
+    psi, _ = orc.advance(p, psi0, 4, fluence=f2)
+    orc.advance(p, psi, 2, fluence=f2)
+    np.testing.assert_allclose(f2, f1, rtol=1e-13, atol=0)
+
+
+def test_green_blocks_counter_clockwise_and_cover_the_band(hq):
+    c = hq.green_block_centres()
+    assert len(c) == 44 == len(set(c))
+    assert c[0] == pytest.approx((-0.175, -0.375)) and c[1] == pytest.approx((-0.125, -0.375))
+    assert c[8] == pytest.approx((0.175, -0.325))  # up the right side after the bottom row
+    assert c[23] == pytest.approx((0.125, 0.375))  # then leftwards along the top
+    assert c[30] == pytest.approx((-0.175, 0.325))  # then down the left side
+    for k in range(44):  # neighbours 0.05 apart, closing the loop
+        (xa, ya), (xb, yb) = c[k], c[(k + 1) % 44]
+        assert math.hypot(xb - xa, yb - ya) == pytest.approx(0.05)
+    # the blocks tile exactly the green cells of the layout
+    for n in (52, 104, 260):
+        p = I.hohlraum(n=n, M=32)
+        xc, yc = _centres(p)
+        cover = np.zeros((n, n), bool)
+        for (bx, by) in c:
+            inx = np.abs(xc - bx) < 0.025
+            iny = np.abs(yc - by) < 0.025
+            assert not np.any(cover[np.ix_(iny, inx)])
+            cover[np.ix_(iny, inx)] = True
+        assert np.array_equal(cover, p.region == GREEN), n
+
+
+@pytest.mark.parametrize("n", [37, 52, 97])
+def test_constant_field(hq, n):
+    p = _uniform_green(n, sigma=10.0)
+    q = hq.qois(p, np.full((n, n), 0.3))
+    assert q["length"] == pytest.approx(2.2, rel=1e-12)
+    np.testing.assert_allclose(q["A"], 3.0, rtol=1e-12)
+    assert q["A_G"] == pytest.approx(3.0, rel=1e-12) and q["A_L"] == pytest.approx(3.0, rel=1e-12)
+    assert abs(q["V_G"]) < 1e-24 and abs(q["V_L"]) < 1e-24
+
+
+@pytest.mark.parametrize("n", [52, 104])
+def test_field_linear_in_x(hq, n):
+    # Phi = x at the cell centre, sigma_a = 10. On aligned grids each block
+    # holds whole cells placed symmetrically about its centre, so A_i = 10 x_i;
+    # on the vertical sides L runs along faces whose two cells average to
+    # +-0.175; on the horizontal sides a is 10 x_c per cell, and the midpoint
+    # rule for x^2 over a cell misses h^3 / 12.
+    p = _uniform_green(n, sigma=10.0)
+    xc, _ = _centres(p)
+    q = hq.qois(p, np.tile(xc, (n, 1)))
+    xs = [bx for bx, _ in hq.green_block_centres()]
+    np.testing.assert_allclose(q["A"], 10 * np.array(xs), rtol=1e-12, atol=1e-13)
+    row = 2 * (0.025 ** 2 + 0.075 ** 2 + 0.125 ** 2 + 0.175 ** 2)
+    assert q["A_G"] == pytest.approx(0.0, abs=1e-13)
+    assert q["V_G"] == pytest.approx(100 * (2 * row + 28 * 0.175 ** 2) / 44, rel=1e-12)
+    h = p.h
+    side = 0.75 * 0.175 ** 2
+    top = 2 * 0.175 ** 3 / 3 - (0.35 / h) * h ** 3 / 12
+    assert q["A_L"] == pytest.approx(0.0, abs=1e-13)
+    assert q["V_L"] == pytest.approx(100 * (2 * side + 2 * top) / 2.2, rel=1e-12)
+
+
+def test_single_cell(hq):
+    # one unit cell next to L inside block 1 (centre (-0.125, -0.375)), just
+    # below the line: block 1 gets sigma h^2 / 0.05^2, the others nothing; L
+    # runs along its top face, where a is half the cell's value, over length h.
+    n = 52
+    p = _uniform_green(n, sigma=10.0)
+    xc, yc = _centres(p)
+    i = int(np.argmin(np.abs(xc - (-0.125 - p.h / 2))))
+    j = int(np.argmin(np.abs(yc - (-0.375 - p.h / 2))))
+    F = np.zeros((n, n))
+    F[j, i] = 1.0
+    q = hq.qois(p, F)
+    want = np.zeros(44)
+    want[1] = 10 * p.h ** 2 / 0.05 ** 2
+    np.testing.assert_allclose(q["A"], want, rtol=1e-12, atol=1e-15)
+    assert q["A_L"] == pytest.approx(5.0 * p.h / 2.2, rel=1e-12)
+    # V_L = (1/|L|) [h (A_L - 5)^2 + (|L| - h) A_L^2]
+    A_L = q["A_L"]
+    assert q["V_L"] == pytest.approx((p.h * (A_L - 5.0) ** 2 + (2.2 - p.h) * A_L ** 2) / 2.2, rel=1e-12)
