@@ -38,6 +38,7 @@ extern "C" {
 
 #define SN_MAX_TALLIES 8   /* absorption tally regions */
 #define SN_MAX_RECTS 4     /* outflow/inflow rectangles */
+#define SN_MAX_FLUENCE_BLOCKS 1024 /* blocks of sn_plan_fluence_functionals */
 #define SN_MAX_REGIONS 256 /* material regions (uint8 ids) */
 #define SN_MAX_ORDINATES 4096
 
@@ -85,6 +86,12 @@ typedef int32_t sn_status;
  *                 0 <= i0 < i1 <= nx, 0 <= j0 < j1 <= ny; the outflow and
  *                 inflow through each rectangle's boundary are QoIs.
  *  psi_dtype      SN_F32 or SN_BF16.
+ *  fluence        1: also accumulate the fluence Phi = int_0^t phi dt per cell
+ *                 in FP64, with the stepper's time rule (Euler dt phi(psi^n);
+ *                 Heun dt/2 (phi(psi^n) + phi(psi^(1)))); the Hohlraum QoI-3
+ *                 to QoI-6 (Sec. 3.2.1) are functionals of sigma_a Phi. Costs
+ *                 8 nx ny bytes of scratch and 20 bytes of traffic per cell and
+ *                 stage. 0: off.
  */
 typedef struct sn_problem {
     int32_t nx, ny;
@@ -105,6 +112,7 @@ typedef struct sn_problem {
     int32_t n_rects;
     const int32_t *rects;
     int32_t psi_dtype;
+    int32_t fluence;
 } sn_problem;
 
 /* Sizes and derived constants of a plan. psi_bytes is the size of ONE angular
@@ -206,6 +214,45 @@ sn_status sn_plan_read_psi(const sn_plan *plan, float *host_out, void *stream);
 /* Copy the current scalar flux phi = sum_k w_k psi_k to host [ny][nx]
  * float32 (the FP32 value the next stage uses). Synchronises `stream`. */
 sn_status sn_plan_read_phi(const sn_plan *plan, float *host_out, void *stream);
+
+/* Copy the fluence Phi (sn_problem.fluence) accumulated since sn_plan_init
+ * to host [ny][nx] float64. Synchronises `stream`. SN_ERR_STATE if the plan
+ * does not accumulate it. */
+sn_status sn_plan_read_fluence(const sn_plan *plan, double *host_out, void *stream);
+
+/* One piece of an integral of a = sigma_a Phi over a set made of cells: the
+ * piece's value is the mean of a over cells cell_a and cell_b (interior
+ * indices j * nx + i; equal for a piece inside one cell, the two cells that
+ * share a face for a piece of a line along that face), and it enters its
+ * set's integral with `weight` (the piece's area or length divided by the
+ * set's, so that a set's weights sum to 1). */
+typedef struct sn_fluence_piece {
+    int32_t cell_a, cell_b;
+    double weight;
+} sn_fluence_piece;
+
+/* Block and line functionals of the fluence (Hohlraum QoI-3 to QoI-6,
+ * Sec. 3.2.1), computed on the device in FP64 in a fixed order. All three
+ * arrays are DEVICE memory owned by the caller (the library allocates
+ * nothing):
+ *  pieces[n_pieces] sorted by set; set g holds pieces [set_start[g],
+ *  set_start[g + 1]) of set_start[n_blocks + 2]: sets 0 .. n_blocks-1 are
+ *  the blocks g_i, set n_blocks is the line L; 1 <= n_blocks <=
+ *  SN_MAX_FLUENCE_BLOCKS.
+ *  out[4 + n_blocks] receives
+ *    out[0] A_G = (1/n_blocks) sum_i A_i   with A_i = sum_{p in g_i} w_p a_p
+ *    out[1] V_G = (1/n_blocks) sum_i (A_G - A_i)^2
+ *    out[2] A_L = sum_{p in L} w_p a_p
+ *    out[3] V_L = sum_{p in L} w_p (A_L - a_p)^2
+ *    out[4 + i] = A_i,
+ *  where a_p is the piece's value (sn_fluence_piece). Uses the fluence as it
+ *  stands after the work queued on `stream`; synchronises `stream`.
+ * SN_ERR_STATE if the plan does not accumulate the fluence; SN_ERR_INVALID
+ * (out filled with NaN) when the kernel finds a cell index out of range, a
+ * non-finite weight, or set_start not non-decreasing from 0 to n_pieces. */
+sn_status sn_plan_fluence_functionals(const sn_plan *plan, const sn_fluence_piece *pieces,
+                                      int32_t n_pieces, const int32_t *set_start,
+                                      int32_t n_blocks, double *out, void *stream);
 
 /* Capture `steps_per_graph` steps (even, >= 2; 0 disables) into a hipGraph
  * and replay it in sn_plan_run. */

@@ -26,12 +26,16 @@ SN_F32 = 0
 SN_BF16 = 1
 MAX_TALLIES = 8
 MAX_RECTS = 4
+MAX_FLUENCE_BLOCKS = 1024
+# sn_fluence_piece: two interior cell indices and the piece's weight
+FLUENCE_PIECE = np.dtype([("cell_a", np.int32), ("cell_b", np.int32), ("weight", np.float64)])
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = [
     "sn_plan_create", "sn_plan_create_tuned", "sn_plan_create_shaped", "sn_plan_get_info", "sn_plan_bind",
     "sn_plan_init", "sn_plan_run", "sn_plan_run_unbounded", "sn_plan_qoi",
-    "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_use_graph", "sn_plan_set_timing",
+    "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_read_fluence", "sn_plan_fluence_functionals",
+    "sn_plan_use_graph", "sn_plan_set_timing",
     "sn_plan_kernel_ms", "sn_plan_destroy", "sn_status_str", "sn_last_error",
     "sn_batch_workspace_bytes", "sn_batch_create", "sn_plan_footprint", "sn_batch_admit", "sn_batch_run",
     "sn_batch_set_steps", "sn_batch_status", "sn_batch_retire", "sn_batch_get_info", "sn_batch_destroy",
@@ -49,7 +53,7 @@ class SnProblem(ctypes.Structure):
         ("region", _vp), ("n_regions", _i32), ("sigma_a", _vp), ("sigma_s", _vp), ("q", _vp),
         ("tally", _vp), ("n_tallies", _i32), ("bc", _i32 * 4), ("inflow", _d * 4),
         ("order", _i32), ("stepper", _i32), ("cfl", _d), ("t_end", _d),
-        ("n_rects", _i32), ("rects", _vp), ("psi_dtype", _i32),
+        ("n_rects", _i32), ("rects", _vp), ("psi_dtype", _i32), ("fluence", _i32),
     ]
 
 
@@ -124,6 +128,8 @@ def lib():
         L.sn_plan_qoi.argtypes = [_vp, ctypes.POINTER(SnQoi), _vp]
         L.sn_plan_read_psi.argtypes = [_vp, _vp, _vp]
         L.sn_plan_read_phi.argtypes = [_vp, _vp, _vp]
+        L.sn_plan_read_fluence.argtypes = [_vp, _vp, _vp]
+        L.sn_plan_fluence_functionals.argtypes = [_vp, _vp, _i32, _vp, _i32, _vp, _vp]
         L.sn_plan_use_graph.argtypes = [_vp, _i32]
         L.sn_plan_set_timing.argtypes = [_vp, _i32]
         L.sn_plan_kernel_ms.argtypes = [_vp, ctypes.POINTER(_d * 4), ctypes.POINTER(ctypes.c_int64 * 4)]
@@ -160,7 +166,7 @@ def check(status: int, where: str):
 class MarshalledProblem:
     """A problem statement laid out as the C struct, owning contiguous copies."""
 
-    def __init__(self, p):
+    def __init__(self, p, fluence: bool = False):
         qd = p.quad
         self.keep = dict(
             xi=np.ascontiguousarray(qd.xi, np.float64), eta=np.ascontiguousarray(qd.eta, np.float64),
@@ -187,4 +193,5 @@ class MarshalledProblem:
         s.cfl, s.t_end = float(p.cfl), float(p.t_end)
         s.n_rects = int(k["rects"].shape[0])
         s.psi_dtype = SN_BF16 if p.psi_dtype == "bf16" else SN_F32
+        s.fluence = 1 if fluence else 0
         self.struct = s

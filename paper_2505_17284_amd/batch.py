@@ -32,9 +32,10 @@ class Busy(RuntimeError):
     """No free slot or not enough budget for the problem right now."""
 
 
-def footprint(problem, rows_per_wave: int = 0, waves_per_group: int = 0, group_size: int = 0) -> int:
+def footprint(problem, rows_per_wave: int = 0, waves_per_group: int = 0, group_size: int = 0,
+              fluence: bool = False) -> int:
     """HBM bytes a problem occupies while admitted (two psi buffers + scratch); host only."""
-    info = solver.plan_info(problem, group_size, rows_per_wave, waves_per_group)
+    info = solver.plan_info(problem, group_size, rows_per_wave, waves_per_group, fluence=fluence)
     return 2 * int(info["psi_bytes"]) + int(info["scratch_bytes"])
 
 
@@ -68,24 +69,27 @@ class Batch:
         torch = solver._torch()
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def footprint(self, problem, group_size: int = 0) -> int:
-        return footprint(problem, self.opts.rows_per_wave, self.opts.waves_per_group, group_size)
+    def footprint(self, problem, group_size: int = 0, fluence: bool = False) -> int:
+        return footprint(problem, self.opts.rows_per_wave, self.opts.waves_per_group, group_size, fluence)
 
-    def fits(self, problem, group_size: int = 0) -> bool:
+    def fits(self, problem, group_size: int = 0, fluence: bool = False) -> bool:
         if len(self.plans) >= self.opts.max_instances:
             return False
         if not self.opts.hbm_budget_bytes:
             return True
-        return self.bytes_admitted + self.footprint(problem, group_size) <= self.opts.hbm_budget_bytes
+        return self.bytes_admitted + self.footprint(problem, group_size, fluence) <= self.opts.hbm_budget_bytes
 
-    def admit(self, problem, psi0=None, group_size: int = 0) -> int:
-        """Allocate, initialise and admit one problem; returns its slot. Raises Busy."""
+    def admit(self, problem, psi0=None, group_size: int = 0, fluence: bool = False) -> int:
+        """Allocate, initialise and admit one problem; returns its slot. Raises Busy.
+        With ``fluence`` the slot's plan also accumulates the time integral of
+        phi (``plan(slot).fluence()``)."""
         if problem.psi_dtype != self.psi_dtype:
             raise ValueError(f"problem stores psi as {problem.psi_dtype}, the batch as {self.psi_dtype}")
-        if not self.fits(problem, group_size):
+        if not self.fits(problem, group_size, fluence):
             raise Busy(f"{problem.name}: no slot or budget free")
         plan = solver.Plan(problem, group_size=group_size, rows_per_wave=self.opts.rows_per_wave,
-                           waves_per_group=self.opts.waves_per_group, device=str(self.device), psi0=psi0)
+                           waves_per_group=self.opts.waves_per_group, device=str(self.device), psi0=psi0,
+                           fluence=fluence)
         slot = ctypes.c_int32(-1)
         st = lib().sn_batch_admit(self.h, plan.h, ctypes.byref(slot))
         if st == SN_ERR_BUSY:
@@ -131,6 +135,10 @@ class Batch:
         info = SnBatchInfo()
         check(lib().sn_batch_get_info(self.h, ctypes.byref(info)), "sn_batch_get_info")
         return {f: getattr(info, f) for f, _ in SnBatchInfo._fields_}
+
+    def plan(self, slot: int):
+        """The plan admitted in ``slot`` (read-only use: the batch advances it)."""
+        return self.plans[slot]
 
     def result(self, slot: int, psi: bool = False, allow_nonfinite: bool = False) -> dict:
         """QoIs of a slot's current state (synchronising), like solver.solve."""

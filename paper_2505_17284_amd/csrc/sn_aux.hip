@@ -123,6 +123,15 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
             acc.w += p.w;
         }
         const int i0 = 4 * c4 - a.ox;  // interior column of the first of the four
+        if (a.fluence != nullptr) {
+            // phi still holds the stage input's scalar flux: add its share of
+            // the time integral before it is replaced
+            const float4 o = *reinterpret_cast<const float4*>(a.phi + off);
+            const float ov[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i0 + e >= 0 && i0 + e < a.nx) a.fluence[(int64_t)j * a.nx + i0 + e] += a.coef * (double)ov[e];
+        }
         if (i0 >= 0 && i0 + 3 < a.nx) {
             *reinterpret_cast<float4*>(a.phi + off) = acc;
         } else {
@@ -190,6 +199,82 @@ __global__ void __launch_bounds__(256) sn_phi_init_kernel(const PhiInitArgs a) {
     a.phi[off] = acc;
 }
 
+// ---------------------------------------------------------------- fluence functionals
+// One workgroup, FP64 throughout, fixed reduction order. The value of a piece
+// is the mean of sigma_a * fluence over its two cells; every set's weighted
+// sum is a strided partial per thread followed by a tree over the workgroup.
+__device__ double fl_block_sum(double v, double* red) {
+    __syncthreads();  // red may still be read by the previous reduction
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+__device__ __forceinline__ double fl_cell(const FluenceArgs& a, int32_t c) {
+    const int32_t j = c / a.nx, i = c - j * a.nx;
+    return a.sa[a.region[a.origin + (int64_t)j * a.pitch + i]] * a.fluence[c];
+}
+
+__global__ void __launch_bounds__(256) sn_fluence_functionals_kernel(const FluenceArgs a) {
+    __shared__ double red[256];
+    __shared__ double setsum[kMaxFluenceBlocks + 1];
+    __shared__ int bad;
+    const int nsets = a.n_blocks + 1;
+    const int64_t ncell = (int64_t)a.nx * a.ny;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int g = threadIdx.x; g <= nsets; g += 256) {
+        const int32_t lo = g == 0 ? 0 : a.set_start[g - 1], hi = a.set_start[g];
+        const bool ok = g == 0 ? hi == 0 : (lo <= hi && (g < nsets || hi == a.n_pieces));
+        if (!ok) atomicOr(&bad, 1);
+    }
+    for (int p = threadIdx.x; p < a.n_pieces; p += 256) {
+        const FluencePiece q = a.pieces[p];
+        if (q.a < 0 || q.a >= ncell || q.b < 0 || q.b >= ncell || !isfinite(q.w)) atomicOr(&bad, 1);
+    }
+    __syncthreads();
+    if (bad) {  // uniform: every thread leaves here
+        if (threadIdx.x == 0) a.status[0] = 1;
+        for (int e = threadIdx.x; e < 4 + a.n_blocks; e += 256) a.out[e] = __builtin_nan("");
+        return;
+    }
+    for (int g = 0; g < nsets; ++g) {
+        double v = 0.0;
+        for (int p = a.set_start[g] + threadIdx.x; p < a.set_start[g + 1]; p += 256) {
+            const FluencePiece q = a.pieces[p];
+            v += q.w * (0.5 * (fl_cell(a, q.a) + fl_cell(a, q.b)));
+        }
+        const double tot = fl_block_sum(v, red);
+        if (threadIdx.x == 0) setsum[g] = tot;
+    }
+    __syncthreads();
+    double A_G = 0.0, V_G = 0.0;
+    for (int g = 0; g < a.n_blocks; ++g) A_G += setsum[g];
+    A_G /= a.n_blocks;
+    for (int g = 0; g < a.n_blocks; ++g) V_G += (A_G - setsum[g]) * (A_G - setsum[g]);
+    V_G /= a.n_blocks;
+    const double A_L = setsum[a.n_blocks];
+    double v = 0.0;
+    for (int p = a.set_start[a.n_blocks] + threadIdx.x; p < a.set_start[a.n_blocks + 1]; p += 256) {
+        const FluencePiece q = a.pieces[p];
+        const double d = A_L - 0.5 * (fl_cell(a, q.a) + fl_cell(a, q.b));
+        v += q.w * d * d;
+    }
+    const double V_L = fl_block_sum(v, red);
+    if (threadIdx.x == 0) {
+        a.out[0] = A_G;
+        a.out[1] = V_G;
+        a.out[2] = A_L;
+        a.out[3] = V_L;
+        a.status[0] = 0;
+    }
+    for (int g = threadIdx.x; g < a.n_blocks; g += 256) a.out[4 + g] = setsum[g];
+}
+
 // ---------------------------------------------------------------- launchers
 bool supported_shape(int rows, int waves) {
     return (rows == 2 || rows == 4) && (waves == 4 || waves == 8);
@@ -231,6 +316,11 @@ hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(sn_ghost_fill_kernel<float>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(sn_ghost_fill_kernel<uint16_t>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fluence_functionals(const FluenceArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(sn_fluence_functionals_kernel, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

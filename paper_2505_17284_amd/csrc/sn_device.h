@@ -29,6 +29,7 @@ constexpr int kGhost = 2;                      // ghost-frame width
 constexpr int kMaxTallies = 8;
 constexpr int kMaxRects = 4;
 constexpr int kMaxQ = 1 + kMaxTallies + 2 * kMaxRects;  // mass, absorption, out, in
+constexpr int kMaxFluenceBlocks = 1024;
 
 enum StageMode : int {
     kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)                   (Euler, Heun stage 1)
@@ -128,6 +129,26 @@ struct FinalizeArgs {
     int32_t* counter;       // stages finalised so far (incremented once per finalize)
     double coef;            // weight of this stage in the time integral
     int32_t n_wg, nq;
+    double* fluence;        // [ny][nx] running time integral of phi, or NULL
+};
+
+// One piece of a block or line integral of sigma_a * fluence (the layout of
+// sn_fluence_piece): the mean over cells a and b, entering with weight w.
+struct FluencePiece {
+    int32_t a, b;
+    double w;
+};
+
+struct FluenceArgs {
+    const double* fluence;      // [ny][nx]
+    const uint8_t* region;      // padded plane: cell (i, j) at origin + j * pitch + i
+    const double* sa;           // [n_regions] sigma_a in FP64
+    const FluencePiece* pieces; // [n_pieces], sorted by set
+    const int32_t* set_start;   // [n_blocks + 2]
+    double* out;                // [4 + n_blocks]
+    int32_t* status;            // 0, or 1 for a malformed piece list
+    int64_t origin;
+    int32_t pitch, nx, ny, n_pieces, n_blocks;
 };
 
 struct PhiInitArgs {
@@ -151,6 +172,7 @@ hipError_t launch_stage_batch(int order, int mode, int dtype, int rows_per_wave,
 hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s);
 hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s);
 hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s);
+hipError_t launch_fluence_functionals(const FluenceArgs& a, hipStream_t s);
 bool supported_shape(int rows_per_wave, int waves);
 
 // Per translation unit (sn_stage_o{1,2}_{f32,bf16}.hip).

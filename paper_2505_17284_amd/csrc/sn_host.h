@@ -62,6 +62,10 @@ struct sn_plan {
     size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
     size_t off_phi = 0, off_phi_part = 0, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
            off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
+    // fluence (time integral of phi per cell, FP64 [ny][nx]) and what its
+    // functionals read: sigma_a in FP64 and a status word
+    bool fluence = false;
+    size_t off_fluence = 0, off_sa64 = 0, off_fstatus = 0;
     double source = 0;  // (sum w) h^2 sum_cells Q
     std::vector<snk::OrdConst> ord_h;
     std::vector<snk::RegConst> reg_h;

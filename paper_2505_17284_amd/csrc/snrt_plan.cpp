@@ -64,6 +64,9 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     if (p->order != 1 && p->order != 2) return fail(SN_ERR_INVALID, "order must be 1 or 2");
     if (p->stepper != SN_EULER && p->stepper != SN_HEUN) return fail(SN_ERR_INVALID, "stepper must be Euler or Heun");
     if (p->psi_dtype != SN_F32 && p->psi_dtype != SN_BF16) return fail(SN_ERR_INVALID, "psi_dtype must be F32 or BF16");
+    if (p->fluence != 0 && p->fluence != 1) return fail(SN_ERR_INVALID, "fluence must be 0 or 1");
+    if (p->fluence && (int64_t)p->nx * p->ny > 0x7fffffff)
+        return fail(SN_ERR_UNSUPPORTED, "fluence needs nx * ny < 2^31 (cell indices are 32-bit)");
     if (!(p->cfl > 0) || !std::isfinite(p->cfl)) return fail(SN_ERR_INVALID, "cfl must be finite and > 0");
     if (!(p->t_end > 0) || !std::isfinite(p->t_end)) return fail(SN_ERR_INVALID, "t_end must be finite and > 0");
 
@@ -153,6 +156,7 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     P->order = p->order;
     P->stepper = p->stepper;
     P->dtype = p->psi_dtype;
+    P->fluence = p->fluence == 1;
     P->cfl = p->cfl;
     P->t_end = p->t_end;
     return SN_OK;
@@ -247,7 +251,13 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     P->off_mass0 = off;
     off += align256(sizeof(double));
     P->off_flags = off;
+    off += align256(2 * sizeof(int32_t));
+    P->off_sa64 = off;
+    off += align256((size_t)P->n_regions * sizeof(double));
+    P->off_fstatus = off;
     off += align256(sizeof(int32_t));
+    P->off_fluence = off;
+    if (P->fluence) off += align256((size_t)P->nx * P->ny * sizeof(double));
     P->scratch_bytes = off;
 
     // Tables, computed in FP64 and rounded once.
@@ -344,6 +354,7 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
     f.n_wg = P->n_wg_l[l];
     f.nq = P->nq;
+    f.fluence = P->fluence ? P->sp<double>(P->off_fluence) : nullptr;
     return f;
 }
 
@@ -585,6 +596,11 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_inst), 0, kMaxQ * sizeof(double), s), "clear QoIs");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_flags), 0, 2 * sizeof(int32_t), s), "clear flags and stage counter");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_phi), 0, P->plane * sizeof(float), s), "clear phi");
+    HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_sa64), P->sa.data(), P->n_regions * sizeof(double),
+                           hipMemcpyHostToDevice, s), "upload sigma_a");
+    if (P->fluence)
+        HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_fluence), 0, (size_t)P->nx * P->ny * sizeof(double), s),
+                "clear fluence");
     HIP_TRY(hipMemsetAsync(P->psi[0], 0, P->psi_bytes, s), "clear psi A");
     HIP_TRY(hipMemsetAsync(P->psi[1], 0, P->psi_bytes, s), "clear psi B");
     P->cur = 0;
@@ -744,6 +760,51 @@ sn_status sn_plan_read_phi(const sn_plan* P, float* host_out, void* stream) {
                              P->pitch * sizeof(float),
                              P->nx * sizeof(float), P->ny, hipMemcpyDeviceToHost, s), "read phi");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return SN_OK;
+}
+
+sn_status sn_plan_read_fluence(const sn_plan* P, double* host_out, void* stream) {
+    if (!P || !host_out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    if (!P->fluence) return fail(SN_ERR_STATE, "plan does not accumulate the fluence");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(host_out, P->sp<char>(P->off_fluence), (size_t)P->nx * P->ny * sizeof(double),
+                           hipMemcpyDeviceToHost, s), "read fluence");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return SN_OK;
+}
+
+sn_status sn_plan_fluence_functionals(const sn_plan* P, const sn_fluence_piece* pieces, int32_t n_pieces,
+                                      const int32_t* set_start, int32_t n_blocks, double* out, void* stream) {
+    static_assert(sizeof(sn_fluence_piece) == sizeof(FluencePiece), "piece layout");
+    if (!P || !set_start || !out || (n_pieces > 0 && !pieces)) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    if (!P->fluence) return fail(SN_ERR_STATE, "plan does not accumulate the fluence");
+    if (n_pieces < 0) return fail(SN_ERR_INVALID, "n_pieces < 0");
+    if (n_blocks < 1 || n_blocks > kMaxFluenceBlocks)
+        return fail(SN_ERR_INVALID, "n_blocks = %d out of range [1, %d]", n_blocks, kMaxFluenceBlocks);
+    if (((uintptr_t)pieces & 7) || ((uintptr_t)set_start & 3) || ((uintptr_t)out & 7))
+        return fail(SN_ERR_INVALID, "misaligned device array");
+    hipStream_t s = (hipStream_t)stream;
+    FluenceArgs a{};
+    a.fluence = P->sp<double>(P->off_fluence);
+    a.region = P->sp<uint8_t>(P->off_region);
+    a.sa = P->sp<double>(P->off_sa64);
+    a.pieces = reinterpret_cast<const FluencePiece*>(pieces);
+    a.set_start = set_start;
+    a.out = out;
+    a.status = P->sp<int32_t>(P->off_fstatus);
+    a.origin = P->origin;
+    a.pitch = P->pitch;
+    a.nx = P->nx;
+    a.ny = P->ny;
+    a.n_pieces = n_pieces;
+    a.n_blocks = n_blocks;
+    HIP_TRY(launch_fluence_functionals(a, s), "fluence functionals launch");
+    int32_t status = -1;
+    HIP_TRY(hipMemcpyAsync(&status, a.status, sizeof status, hipMemcpyDeviceToHost, s), "read status");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (status != 0) return fail(SN_ERR_INVALID, "malformed piece list (cell index, weight or set_start)");
     return SN_OK;
 }
 

@@ -13,8 +13,8 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (MAX_RECTS, MAX_TALLIES, SN_ERR_NONFINITE, MarshalledProblem, SnError,
-                   SnPlanInfo, SnQoi, check, lib)
+from ._lib import (FLUENCE_PIECE, MAX_FLUENCE_BLOCKS, MAX_RECTS, MAX_TALLIES, SN_ERR_NONFINITE,
+                   MarshalledProblem, SnError, SnPlanInfo, SnQoi, check, lib)
 
 
 def _torch():
@@ -26,10 +26,10 @@ def _torch():
 
 
 def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
-              group_size_average: int = 0) -> dict:
+              group_size_average: int = 0, fluence: bool = False) -> dict:
     """Derived constants and buffer sizes of a plan (host only, no GPU).
     group_size applies to both stages unless group_size_average is given."""
-    m = MarshalledProblem(problem)
+    m = MarshalledProblem(problem, fluence)
     h = ctypes.c_void_p()
     check(lib().sn_plan_create_shaped(ctypes.byref(m.struct), group_size, group_size_average or group_size,
                                       rows_per_wave, waves_per_group, ctypes.byref(h)), "sn_plan_create")
@@ -61,12 +61,13 @@ class Plan:
     """A bound, initialised solve on one GPU."""
 
     def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
-                 device: str = "cuda:0", psi0=None, graph_steps: int = 0, group_size_average: int = 0):
+                 device: str = "cuda:0", psi0=None, graph_steps: int = 0, group_size_average: int = 0,
+                 fluence: bool = False):
         torch = _torch()
         assert problem.n_tallies <= MAX_TALLIES and problem.n_rects <= MAX_RECTS
         self.problem = problem
         self.device = torch.device(device)
-        self._m = MarshalledProblem(problem)
+        self._m = MarshalledProblem(problem, fluence)
         self.h = ctypes.c_void_p()
         check(lib().sn_plan_create_shaped(ctypes.byref(self._m.struct), group_size,
                                           group_size_average or group_size, rows_per_wave,
@@ -130,6 +131,31 @@ class Plan:
         out = np.empty((p.ny, p.nx), dtype=np.float32)
         check(lib().sn_plan_read_phi(self.h, out.ctypes.data, self.stream), "sn_plan_read_phi")
         return out
+
+    def fluence(self) -> np.ndarray:
+        """Time integral of phi per cell since init ([ny][nx] float64); the
+        plan must have been made with ``fluence=True``."""
+        p = self.problem
+        out = np.empty((p.ny, p.nx), dtype=np.float64)
+        check(lib().sn_plan_read_fluence(self.h, out.ctypes.data, self.stream), "sn_plan_read_fluence")
+        return out
+
+    def fluence_functionals(self, pieces: np.ndarray, set_start: np.ndarray, n_blocks: int) -> dict:
+        """Block and line functionals of sigma_a * fluence, on the device
+        (sn_plan_fluence_functionals): A_G, V_G, A_L, V_L and the block means A."""
+        torch = _torch()
+        pieces = np.ascontiguousarray(pieces, dtype=FLUENCE_PIECE)
+        set_start = np.ascontiguousarray(set_start, dtype=np.int32)
+        if not 1 <= n_blocks <= MAX_FLUENCE_BLOCKS or set_start.shape != (n_blocks + 2,):
+            raise ValueError("set_start must hold n_blocks + 2 entries, 1 <= n_blocks <= %d" % MAX_FLUENCE_BLOCKS)
+        raw = torch.from_numpy(pieces.view(np.uint8).reshape(-1)).to(self.device) if len(pieces) else None
+        ss = torch.from_numpy(set_start).to(self.device)
+        out = torch.empty(4 + n_blocks, dtype=torch.float64, device=self.device)
+        check(lib().sn_plan_fluence_functionals(self.h, raw.data_ptr() if raw is not None else None,
+                                                int(len(pieces)), ss.data_ptr(), int(n_blocks),
+                                                out.data_ptr(), self.stream), "sn_plan_fluence_functionals")
+        o = out.cpu().numpy()
+        return dict(A_G=float(o[0]), V_G=float(o[1]), A_L=float(o[2]), V_L=float(o[3]), A=o[4:].copy())
 
     def set_timing(self, on: bool):
         check(lib().sn_plan_set_timing(self.h, 1 if on else 0), "sn_plan_set_timing")

@@ -5,6 +5,9 @@ value here comes from the HIP path.
 
     python tests/golden/make_oracle_goldens.py lattice700   # ~10 min on 8 cores
     python tests/golden/make_oracle_goldens.py hohlraum260  # ~2 min on 8 cores
+
+Hohlraum cases also store the green-band QoI-3 to QoI-6 of the oracle's
+fluence (oracle/hohlraum_qoi.py).
 """
 
 import json
@@ -18,6 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
+from oracle import hohlraum_qoi  # noqa: E402
 from paper_2505_17284_amd import inputs as I  # noqa: E402
 
 CASES = {
@@ -33,7 +37,8 @@ def main(names):
         fname, make = CASES[name]
         p = make()
         t0 = time.time()
-        r = oracle.solve(p)
+        hohl = p.meta.get("kind") == "hohlraum"
+        r = oracle.solve(p, fluence=hohl)
         out = dict(
             problem=p.name, nx=p.nx, ny=p.ny, M=p.M, order=p.order, stepper=p.stepper,
             nt=r["nt"], dt=r["dt"], t=r["t"],
@@ -43,6 +48,10 @@ def main(names):
             host=platform.processor() or platform.machine(),
             writer="tests/golden/make_oracle_goldens.py (FP64 oracle only)",
         )
+        if hohl:
+            band = hohlraum_qoi.qois(p, r["fluence"])
+            out["green_band"] = {k: float(band[k]) for k in ("A_G", "V_G", "A_L", "V_L", "length")}
+            out["green_band"]["A"] = [float(a) for a in band["A"]]
         with open(os.path.join(HERE, fname), "w") as f:
             json.dump(out, f, indent=1)
         print(name, "done in", round(out["oracle_seconds"], 1), "s", flush=True)

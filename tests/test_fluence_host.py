@@ -1,0 +1,47 @@
+"""Host side of the fluence functionals: the green-band geometry that the
+device sums over (no GPU). Evaluating the product's pieces with numpy must
+give the oracle's QoI-3 to QoI-6 (Sec. 3.2.1) on aligned and unaligned grids;
+the weights of every block and of the line sum to one."""
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import hohlraum as H
+from paper_2505_17284_amd import inputs as I
+
+
+def _eval(p, F, pieces, starts, nb):
+    a = (np.asarray(p.sigma_a)[p.region] * F).reshape(-1)
+    val = 0.5 * (a[pieces["cell_a"]] + a[pieces["cell_b"]])
+    S = np.array([np.sum(pieces["weight"][starts[g]:starts[g + 1]] * val[starts[g]:starts[g + 1]])
+                  for g in range(nb + 1)])
+    A = S[:nb]
+    A_G = A.mean()
+    line = slice(starts[nb], starts[nb + 1])
+    A_L = S[nb]
+    return dict(A_G=A_G, V_G=np.mean((A_G - A) ** 2), A_L=A_L,
+                V_L=np.sum(pieces["weight"][line] * (A_L - val[line]) ** 2), A=A)
+
+
+def test_block_centres_match_the_oracle():
+    from oracle import hohlraum_qoi
+    np.testing.assert_allclose(np.array(H.block_centres()), np.array(hohlraum_qoi.green_block_centres()),
+                               rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [52, 60, 97, 260])
+def test_pieces_reproduce_oracle_qois(n):
+    from oracle import hohlraum_qoi
+    p = I.hohlraum(n=n, M=32)
+    F = np.random.Generator(np.random.PCG64(n)).uniform(0.0, 2.0, (n, n))
+    pieces, starts, nb = H.green_band_pieces(p)
+    assert nb == 44 and starts.shape == (46,) and starts[0] == 0 and starts[-1] == len(pieces)
+    assert np.all(np.diff(starts) > 0)
+    for g in range(nb + 1):
+        assert pieces["weight"][starts[g]:starts[g + 1]].sum() == pytest.approx(1.0, rel=1e-12)
+    assert pieces["cell_a"].min() >= 0 and pieces["cell_b"].max() < n * n
+    got = _eval(p, F, pieces, starts, nb)
+    want = hohlraum_qoi.qois(p, F)
+    np.testing.assert_allclose(got["A"], want["A"], rtol=1e-12)
+    for k in ("A_G", "V_G", "A_L", "V_L"):
+        assert got[k] == pytest.approx(want[k], rel=1e-11), k

@@ -1,0 +1,191 @@
+"""Fluence (time-integrated scalar flux) and the Hohlraum green-band QoIs on
+the GPU, through the C ABI, against the FP64 oracle.
+
+The device adds coef * phi(stage input) per cell in the QoI finalize of every
+stage; the oracle adds the same time rule to its FP64 phi. Elementwise the
+two agree to the field tolerance of the stages run; the green-band
+functionals (QoI-3 to QoI-6, Sec. 3.2.1) of the device fluence, summed on the
+device, agree with the oracle's functionals of its own fluence to the QoI
+tolerance. A batch member accumulates the same fluence bit for bit.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+from tests.parity import compare_field
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17284_amd import solver
+
+    return solver
+
+
+def _gpu(sv, p, steps, psi0=None, **kw):
+    print(f"[case] fluence {p.name} n=({p.nx},{p.ny}) M={p.M} order={p.order} stepper={p.stepper} "
+          f"steps={steps} kw={kw}", flush=True)
+    plan = sv.Plan(p, psi0=psi0, fluence=True, **kw)
+    try:
+        plan.run(steps)
+        from paper_2505_17284_amd import hohlraum
+        band = hohlraum.green_band_qois(plan) if p.meta.get("kind") == "hohlraum" else None
+        return plan.fluence(), plan.qoi(), band
+    finally:
+        plan.close()
+
+
+def _check_band(g, o, rtol=1e-5):
+    for k in ("A_G", "A_L"):
+        assert g[k] == pytest.approx(o[k], rel=rtol), (k, g[k], o[k])
+    # the spreads are differences of values resolved to rtol: hold them to
+    # rtol of the squared mean they are measured against
+    for k, m in (("V_G", "A_G"), ("V_L", "A_L")):
+        assert abs(g[k] - o[k]) <= rtol * (abs(o[k]) + o[m] ** 2), (k, g[k], o[k])
+    scale = np.abs(o["A"]).max()
+    np.testing.assert_allclose(g["A"], o["A"], rtol=rtol, atol=rtol * scale)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("stepper", [I.EULER, I.HEUN])
+def test_fluence_matches_oracle_elementwise(sv, orc, order, stepper):
+    """Ragged 130 x 37 grid, random materials and state, several tiles."""
+    p = I.random_materials(130, 37, 5, seed=11, M=32, order=order, stepper=stepper,
+                           bc=(I.BC_REFLECT, I.BC_INFLOW, I.BC_INFLOW, I.BC_VACUUM), inflow=(0, 0.7, 0.3, 0))
+    psi0 = I.random_state(p, 12)
+    steps = 5
+    fl, q, _ = _gpu(sv, p, steps, psi0=psi0)
+    o = orc.solve(p, steps=steps, psi0=psi0, fluence=True)
+    stages = steps * (2 if stepper == I.HEUN else 1)
+    ok, rep = compare_field(fl, o["fluence"], stages)
+    print("fluence:", rep)
+    assert ok, rep
+    # the device's own integrated mass is h^2 sum Phi
+    assert q["qoi_int"]["mass"] == pytest.approx(p.h * p.h * fl.sum(), rel=1e-5)
+
+
+def test_fluence_off_is_rejected_and_batch_member_bit_identical(sv):
+    from paper_2505_17284_amd import batch
+    from paper_2505_17284_amd._lib import SnError
+
+    p = I.hohlraum(104, 32, t_end=0.2)
+    plan = sv.Plan(p)
+    try:
+        with pytest.raises(SnError):
+            plan.fluence()
+    finally:
+        plan.close()
+    alone, _, band = _gpu(sv, p, None, rows_per_wave=2, waves_per_group=4)
+    print("[case] fluence batch member", flush=True)
+    b = batch.Batch(max_instances=4, steps_per_run=7)
+    try:
+        s0 = b.admit(I.lattice(70, 32, order=2, stepper=I.HEUN, t_end=0.3))
+        s1 = b.admit(p, fluence=True)
+        while b.unfinished():
+            b.run()
+        from paper_2505_17284_amd import hohlraum
+        assert np.array_equal(b.plan(s1).fluence(), alone)
+        bb = hohlraum.green_band_qois(b.plan(s1))
+        assert bb["A_G"] == band["A_G"] and bb["V_L"] == band["V_L"]
+        assert b.status(s0)[0]
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_hohlraum_green_band_few_steps(sv, orc, order):
+    """Hohlraum layout, random state: fluence and the four green-band QoIs
+    after three Heun steps (sigma_a differs across the band's cells)."""
+    from oracle import hohlraum_qoi
+
+    p = I.hohlraum(130, 32, order=order)
+    psi0 = I.random_state(p, 78, "smooth")
+    fl, _, band = _gpu(sv, p, 3, psi0=psi0)
+    o = orc.solve(p, steps=3, psi0=psi0, fluence=True)
+    ok, rep = compare_field(fl, o["fluence"], 6)
+    print("fluence:", rep)
+    assert ok, rep
+    ob = hohlraum_qoi.qois(p, o["fluence"])
+    print({k: (band[k], ob[k]) for k in ("A_G", "V_G", "A_L", "V_L")})
+    _check_band(band, ob)
+
+
+@pytest.mark.parametrize("n", [97, 156])
+def test_green_band_functionals_on_unaligned_and_aligned_grids(sv, orc, n):
+    """The device functionals of the device fluence vs the oracle functionals
+    of the same field read back (isolates the summation kernel: 1e-12), and
+    vs the oracle's own fluence (1e-5)."""
+    from oracle import hohlraum_qoi
+
+    p = I.hohlraum(n, 32, order=2, t_end=0.1)
+    fl, _, band = _gpu(sv, p, None)
+    same = hohlraum_qoi.qois(p, fl)
+    for k in ("A_G", "V_G", "A_L", "V_L"):
+        assert band[k] == pytest.approx(same[k], rel=1e-12, abs=1e-300), k
+    np.testing.assert_allclose(band["A"], same["A"], rtol=1e-12, atol=0)
+    o = orc.solve(p, fluence=True)
+    _check_band(band, hohlraum_qoi.qois(p, o["fluence"]))
+
+
+def test_functionals_reject_malformed_piece_lists(sv):
+    """Bad set boundaries and cell indices are caught on the device before any
+    access through them; the call reports SN_ERR_INVALID and fills NaN."""
+    from paper_2505_17284_amd import hohlraum
+    from paper_2505_17284_amd._lib import SnError
+
+    p = I.hohlraum(52, 32, t_end=0.05)
+    plan = sv.Plan(p, fluence=True)
+    try:
+        plan.run()
+        pieces, starts, nb = hohlraum.green_band_pieces(p)
+        good = plan.fluence_functionals(pieces, starts, nb)
+        assert np.isfinite(good["A_G"])
+        bad = starts.copy()
+        bad[-1] -= 1
+        with pytest.raises(SnError):
+            plan.fluence_functionals(pieces, bad, nb)
+        bad = starts.copy()
+        bad[3], bad[4] = bad[4], bad[3]
+        with pytest.raises(SnError):
+            plan.fluence_functionals(pieces, bad, nb)
+        bp = pieces.copy()
+        bp["cell_b"][5] = p.nx * p.ny
+        with pytest.raises(SnError):
+            plan.fluence_functionals(bp, starts, nb)
+        bp = pieces.copy()
+        bp["weight"][0] = np.inf
+        with pytest.raises(SnError):
+            plan.fluence_functionals(bp, starts, nb)
+        again = plan.fluence_functionals(pieces, starts, nb)
+        assert again["A_G"] == good["A_G"] and again["V_L"] == good["V_L"]
+    finally:
+        plan.close()
+
+
+def test_hohlraum260_full_run_green_band_matches_golden(sv):
+    """Full Hohlraum solve (260^2, 256 ordinates, minmod, Heun, 1040 steps):
+    QoI-3 to QoI-6 against the oracle's values stored by
+    tests/golden/make_oracle_goldens.py."""
+    path = os.path.join(GOLDEN, "oracle_hohlraum260_M256_heun2.json")
+    with open(path) as f:
+        gold = json.load(f)
+    if "green_band" not in gold:
+        pytest.skip("golden has no green-band QoIs")
+    p = I.hohlraum(260, 256)
+    _, _, band = _gpu(sv, p, None)
+    gb = dict(gold["green_band"])
+    gb["A"] = np.array(gb["A"])
+    print({k: (band[k], gb[k]) for k in ("A_G", "V_G", "A_L", "V_L")})
+    _check_band(band, gb, rtol=1e-4)
