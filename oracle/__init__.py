@@ -52,6 +52,32 @@ class _Prob(ctypes.Structure):
     ]
 
 
+class _Probes(ctypes.Structure):
+    _fields_ = [
+        ("n_probes", ctypes.c_int), ("n_windows", ctypes.c_int), ("n_cells", ctypes.c_int),
+        ("cell_i", ctypes.c_void_p), ("cell_j", ctypes.c_void_p), ("probe", ctypes.c_void_p),
+        ("weight", ctypes.c_void_p),
+    ]
+
+
+class _MarshalledProbes:
+    """probes: dict with n_probes, n_windows and per-cell arrays cell_i,
+    cell_j, probe, weight (see oracle.hohlraum_qoi.probe_cells)."""
+
+    def __init__(self, pr):
+        self.arrs = dict(cell_i=np.ascontiguousarray(pr["cell_i"], np.int32),
+                         cell_j=np.ascontiguousarray(pr["cell_j"], np.int32),
+                         probe=np.ascontiguousarray(pr["probe"], np.int32),
+                         weight=np.ascontiguousarray(pr["weight"], np.float64))
+        s = _Probes()
+        s.n_probes, s.n_windows = int(pr["n_probes"]), int(pr["n_windows"])
+        s.n_cells = int(self.arrs["weight"].shape[0])
+        for k, a in self.arrs.items():
+            setattr(s, k, a.ctypes.data)
+        self.s = s
+        self.ref = ctypes.byref(s)
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -73,7 +99,7 @@ def _load():
         lib.orc_qoi_len.argtypes = [P]
         lib.orc_qoi_len.restype = ctypes.c_int
         lib.orc_qoi.argtypes = [P, d, d, d]
-        lib.orc_advance.argtypes = [P, ctypes.c_int, d, d, d]
+        lib.orc_advance.argtypes = [P, ctypes.c_int, d, d, d, ctypes.POINTER(_Probes), ctypes.c_int, d]
         lib.orc_advance.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -180,11 +206,14 @@ def qoi(p, psi):
     return qv
 
 
-def advance(p, psi, n_steps, qint=None, fluence=None):
+def advance(p, psi, n_steps, qint=None, fluence=None, probes=None, step0=0, probe_acc=None):
     """Advance a copy of ``psi`` by ``n_steps``; returns (psi, qint).
 
     With ``fluence`` (an [ny][nx] array, updated in place) the time integral
-    of phi over the steps is added to it with the stepper's rule.
+    of phi over the steps is added to it with the stepper's rule. With
+    ``probes`` and ``probe_acc`` ([n_windows][n_probes][3], updated in place)
+    the probes' window averages of phi, J_x, J_y are accumulated; ``step0`` is
+    the index of the first step taken (it decides the windows).
     """
     m = _Marshalled(p)
     a = _state(m, psi).copy()
@@ -195,30 +224,43 @@ def advance(p, psi, n_steps, qint=None, fluence=None):
         if fluence.shape != (m.ny, m.nx) or fluence.dtype != np.float64 or not fluence.flags.c_contiguous:
             raise ValueError("fluence must be a C-contiguous float64 [ny][nx] array")
         fl = fluence.ctypes.data
-    rc = _load().orc_advance(m.ref, int(n_steps), a.ctypes.data, qi.ctypes.data, fl)
+    mp, pa = None, None
+    if probes is not None:
+        mp = _MarshalledProbes(probes)
+        shape = (mp.s.n_windows, mp.s.n_probes, 3)
+        if probe_acc is None or probe_acc.shape != shape or probe_acc.dtype != np.float64 \
+                or not probe_acc.flags.c_contiguous:
+            raise ValueError("probe_acc must be a C-contiguous float64 array of shape %s" % (shape,))
+        pa = probe_acc.ctypes.data
+    rc = _load().orc_advance(m.ref, int(n_steps), a.ctypes.data, qi.ctypes.data, fl,
+                             mp.ref if mp is not None else None, int(step0), pa)
     if rc != 0:
         raise MemoryError("oracle could not allocate its work arrays")
     return a, qi
 
 
-def solve(p, steps=None, psi0=None, fluence=False):
+def solve(p, steps=None, psi0=None, fluence=False, probes=None):
     """Run the problem from psi0 (default 0) for ``steps`` (default N_t) steps.
 
     Returns a dict: psi, phi, nt, dt, steps, t, qoi (instantaneous at the end),
-    qoi_int (time integrals), names, seconds, and with ``fluence`` the time
-    integral of phi per cell ("fluence", [ny][nx]).
+    qoi_int (time integrals), names, seconds, with ``fluence`` the time
+    integral of phi per cell ("fluence", [ny][nx]), and with ``probes`` the
+    probes' window averages ("probes", [n_windows][n_probes][phi, J_x, J_y]).
     """
     nt, dt = num_steps(p)
     steps = nt if steps is None else int(steps)
     if psi0 is None:
         psi0 = np.zeros((p.quad.M, p.ny, p.nx))
     fl = np.zeros((p.ny, p.nx)) if fluence else None
+    pacc = None if probes is None else np.zeros((int(probes["n_windows"]), int(probes["n_probes"]), 3))
     t0 = time.perf_counter()
-    psi, qint = advance(p, psi0, steps, fluence=fl)
+    psi, qint = advance(p, psi0, steps, fluence=fl, probes=probes, probe_acc=pacc)
     secs = time.perf_counter() - t0
     out = dict(psi=psi, phi=scalar_flux(p, psi), nt=nt, dt=dt, steps=steps,
                t=steps * dt, qoi=qoi(p, psi), qoi_int=qint, names=qoi_names(p),
                seconds=secs)
     if fluence:
         out["fluence"] = fl
+    if probes is not None:
+        out["probes"] = pacc
     return out

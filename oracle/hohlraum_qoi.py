@@ -1,4 +1,4 @@
-"""Hohlraum QoI-3 to QoI-6 from a fluence field (test infrastructure).
+"""Hohlraum QoI-1 probes and QoI-3 to QoI-6 from a fluence field (test infrastructure).
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package: the parity tests and
 the script that writes the stored expected values use it; the product path
@@ -17,6 +17,11 @@ a(x, y) = sigma_a(x, y) Phi(x, y) over the green capsule band:
          centres (the rectangle with corners (+-0.175, +-0.375), length 2.2);
   QoI-6  V_L = (1/length(L)) int_L |A_L - a|^2 ds.
 
+QoI-1 averages phi, J_x and J_y over a ball B_r (r = 0.01) around each of
+four probe points and over each tenth of [0, T], divided by the space-time
+volume |B_r| T/10 (``probe_cells`` gives each cell's weight, the area of the
+cell inside the ball over |B_r|; the oracle's stepping does the rest).
+
 Readings where the paper is silent: a block mean weights every cell by the
 area it shares with the block (exact for the cell-constant solution); where
 L runs along a cell face, a on L is the mean of the two cells that share the
@@ -29,6 +34,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+from scipy import integrate
 
 BLOCK = 0.05
 N_BLOCKS = 44
@@ -130,3 +136,55 @@ def qois(p, fluence):
     A_L = sum(d * v for d, v in vals) / length
     V_L = sum(d * (A_L - v) ** 2 for d, v in vals) / length
     return dict(A_G=A_G, V_G=V_G, A_L=float(A_L), V_L=float(V_L), A=A, length=length)
+
+
+PROBE_CENTRES = [(-0.4, 0.0), (0.4, 0.0), (0.0, -0.5), (0.0, 0.5)]
+PROBE_RADIUS = 0.01
+N_WINDOWS = 10
+
+
+def disc_cell_area(cx, cy, r, x0, x1, y0, y1):
+    """Area of the disc of radius r about (cx, cy) inside [x0, x1] x [y0, y1],
+    by adaptive quadrature of the disc's vertical chord clipped to the cell."""
+    a, b = max(x0, cx - r), min(x1, cx + r)
+    if b <= a:
+        return 0.0
+
+    def chord(x):
+        s = math.sqrt(max(r * r - (x - cx) ** 2, 0.0))
+        return max(0.0, min(y1, cy + s) - max(y0, cy - s))
+
+    kinks = []
+    for yb in (y0, y1):  # where the circle crosses the cell's horizontal edges
+        d = yb - cy
+        if abs(d) < r:
+            for sgn in (-1, 1):
+                x = cx + sgn * math.sqrt(r * r - d * d)
+                if a < x < b:
+                    kinks.append(x)
+    val, _ = integrate.quad(chord, a, b, points=sorted(kinks) or None, epsabs=1e-17, epsrel=1e-13,
+                            limit=200)
+    return val
+
+
+def probe_cells(p, centres=PROBE_CENTRES, r=PROBE_RADIUS, n_windows=N_WINDOWS):
+    """Cells of every probe ball with weight = (area of the cell in the ball) / (pi r^2),
+    as the dict ``oracle.solve(..., probes=...)`` takes."""
+    ci, cj, pr, wt = [], [], [], []
+    for q, (cx, cy) in enumerate(centres):
+        for j in range(p.ny):
+            y0, y1 = p.y0 + j * p.h, p.y0 + (j + 1) * p.h
+            if y1 <= cy - r or y0 >= cy + r:
+                continue
+            for i in range(p.nx):
+                x0, x1 = p.x0 + i * p.h, p.x0 + (i + 1) * p.h
+                if x1 <= cx - r or x0 >= cx + r:
+                    continue
+                area = disc_cell_area(cx, cy, r, x0, x1, y0, y1)
+                if area > 1e-9 * p.h * p.h:  # not a rounding sliver of a cell the disc only touches
+                    ci.append(i)
+                    cj.append(j)
+                    pr.append(q)
+                    wt.append(area / (math.pi * r * r))
+    return dict(n_probes=len(centres), n_windows=n_windows, cell_i=np.array(ci), cell_j=np.array(cj),
+                probe=np.array(pr), weight=np.array(wt))

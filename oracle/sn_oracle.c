@@ -21,6 +21,8 @@
  *     eq. eq_ODE; dt = CFL * dx: Sec. 5.1.3.
  *   - QoIs: mass (QoI-5), absorption per region (QoI-3/4), outflow through the
  *     boundary of a rectangle (QoI-1/2): Sec. 3.1.2.
+ *   - optional: the time integral of phi per cell (fluence) and space-time
+ *     probe averages of phi, J_x, J_y (the Hohlraum QoIs of Sec. 3.2.1).
  * The readings taken where the paper is silent (minmod reconstruction on the
  * Cartesian grid, reflective walls, the time rule for integrated QoIs, the
  * boundary-slope rule) are listed in the design notes and restated where they
@@ -277,19 +279,57 @@ static void add_fluence(const orc_problem *P, double coef, const double *phi, do
     for (c = 0; c < ncell; ++c) fluence[c] += coef * phi[c];
 }
 
-int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint, double *fluence)
+/* Space-time probes (Hohlraum QoI-1, Sec. 3.2.1): probe p averages phi,
+ * J_x = sum_l w_l xi_l psi_l and J_y = sum_l w_l eta_l psi_l over its cells
+ * with the given weights (area of the cell inside the probe's ball over the
+ * ball's area) and over each of n_windows equal time windows of [0, T]. A
+ * step's contributions (the same time rule as the integrated QoIs) fall in the
+ * window that holds the step's start time: window floor(step n_windows / N_t). */
+typedef struct {
+    int n_probes, n_windows, n_cells;
+    const int *cell_i, *cell_j, *probe; /* [n_cells] */
+    const double *weight;               /* [n_cells] */
+} orc_probes;
+
+static void add_probes(const orc_problem *P, const orc_probes *pr, int step, int nt, double coef,
+                       const double *psi, double *pacc)
+{
+    int c, k, w;
+    double win;
+    if (!pr || !pacc || pr->n_probes <= 0) return;
+    w = (int)(((long long)step * pr->n_windows) / nt);
+    if (w >= pr->n_windows) return;
+    win = P->t_end / pr->n_windows; /* the window's length: the average's time measure */
+    for (c = 0; c < pr->n_cells; ++c) {
+        double m0 = 0.0, mx = 0.0, my = 0.0;
+        double *a = &pacc[((size_t)w * pr->n_probes + pr->probe[c]) * 3];
+        for (k = 0; k < P->M; ++k) {
+            double v = PSI(P, psi, k, pr->cell_j[c], pr->cell_i[c]);
+            m0 += P->w[k] * v;
+            mx += P->w[k] * P->xi[k] * v;
+            my += P->w[k] * P->eta[k] * v;
+        }
+        a[0] += coef / win * pr->weight[c] * m0;
+        a[1] += coef / win * pr->weight[c] * mx;
+        a[2] += coef / win * pr->weight[c] * my;
+    }
+}
+
+int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint, double *fluence,
+                const orc_probes *probes, int step0, double *pacc)
 {
     size_t n = (size_t)P->M * P->nx * P->ny;
     size_t ncell = (size_t)P->nx * P->ny;
     int L = orc_qoi_len(P);
     double dt;
+    int nt;
     double *F = malloc(n * sizeof(double));
     double *psi1 = P->stepper == 1 ? malloc(n * sizeof(double)) : NULL;
     double *phi = malloc(ncell * sizeof(double));
     double *qv = malloc((size_t)L * sizeof(double));
     int s, t;
     long long e;
-    orc_num_steps(P, &dt);
+    nt = orc_num_steps(P, &dt);
     if (!F || !phi || !qv || (P->stepper == 1 && !psi1)) {
         free(F); free(psi1); free(phi); free(qv);
         return -1;
@@ -301,11 +341,13 @@ int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint, do
         if (P->stepper == 0) {
             for (t = 0; t < L; ++t) qint[t] += dt * qv[t];
             add_fluence(P, dt, phi, fluence);
+            add_probes(P, probes, step0 + s, nt, dt, psi, pacc);
 #pragma omp parallel for
             for (e = 0; e < (long long)n; ++e) psi[e] = psi[e] + dt * F[e];
         } else {
             for (t = 0; t < L; ++t) qint[t] += 0.5 * dt * qv[t];
             add_fluence(P, 0.5 * dt, phi, fluence);
+            add_probes(P, probes, step0 + s, nt, 0.5 * dt, psi, pacc);
 #pragma omp parallel for
             for (e = 0; e < (long long)n; ++e) psi1[e] = psi[e] + dt * F[e];
             orc_scalar_flux(P, psi1, phi);
@@ -313,6 +355,7 @@ int orc_advance(const orc_problem *P, int n_steps, double *psi, double *qint, do
             orc_rhs(P, psi1, phi, F);
             for (t = 0; t < L; ++t) qint[t] += 0.5 * dt * qv[t];
             add_fluence(P, 0.5 * dt, phi, fluence);
+            add_probes(P, probes, step0 + s, nt, 0.5 * dt, psi1, pacc);
 #pragma omp parallel for
             for (e = 0; e < (long long)n; ++e) {
                 double psi2 = psi1[e] + dt * F[e];
