@@ -98,17 +98,14 @@ def cpu_baseline(problem, budget_s=15.0):
                       f"(FP64, {threads} OpenMP threads, {secs:.1f} s)"}
 
 
-def time_cavity(steps, dtype, warmup=3):
-    """Heun steps of the full-size walled cavity (1300^2 cells, 512 ordinates,
-    3.5 GB per FP32 psi buffer): the same kernels on a state far larger than
-    the 256 MB Infinity Cache."""
+def time_workload(p, workload, steps, warmup=3):
+    """Heun steps of another full-size workload on the same kernels: per-step
+    time, updates/s and the two stage kernels' algorithmic rates."""
     import torch
 
-    from paper_2505_17284_amd import inputs as I
     from paper_2505_17284_amd import solver
 
-    p = I.config(3).replace(psi_dtype=dtype)
-    print(f"[bench] cavity: {p.name} {steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] {workload}: {p.name} {steps} steps", file=sys.stderr, flush=True)
     plan = solver.Plan(p, device="cuda:0")
     try:
         plan.run(warmup, unbounded=True)
@@ -127,11 +124,30 @@ def time_cavity(steps, dtype, warmup=3):
     s1 = ms[1] / max(counts[1], 1)
     b2 = algorithmic_bytes(p, info, 2)
     b1 = algorithmic_bytes(p, info, 1)
-    return {"workload": "cavity1300_M512_heun2", "steps": steps, "ms_per_step": secs * 1e3 / steps,
+    return {"workload": workload, "steps": steps, "ms_per_step": secs * 1e3 / steps,
             "updates_per_s": p.cell_ordinates * steps / secs, "stage2_kernel_ms": s2,
             "stage2_achieved_GBs": b2 / (s2 * 1e-3) / 1e9, "stage2_frac": b2 / (s2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "stage1_kernel_ms": s1, "stage1_achieved_GBs": b1 / (s1 * 1e-3) / 1e9,
-            "step_algorithmic_GBs": (b1 + b2) / (secs / steps) / 1e9}
+            "step_algorithmic_GBs": (b1 + b2) / (secs / steps) / 1e9,
+            "ordinates_per_group": [info["group_size"], info["group_size_average"]]}
+
+
+def time_cavity(steps, dtype, warmup=3):
+    """The full-size walled cavity (1300^2 cells, 512 ordinates, 3.5 GB per
+    FP32 psi buffer): a state far larger than the 256 MB Infinity Cache."""
+    from paper_2505_17284_amd import inputs as I
+
+    return time_workload(I.config(3).replace(psi_dtype=dtype), "cavity1300_M512_heun2", steps, warmup)
+
+
+def time_tessellation(steps, dtype, N=22, warmup=2):
+    """The lattice at 700^2 with the paper's tessellation quadrature at its
+    finest N = 22 (M = 4 N^2 = 1936 ordinates, 3.8 GB per FP32 psi buffer)."""
+    from paper_2505_17284_amd import inputs as I
+
+    p = I.lattice(700, order=2, stepper=I.HEUN, quad=I.tessellation_quadrature(N), psi_dtype=dtype,
+                  name=f"lattice700_tess{N}")
+    return time_workload(p, f"lattice700_tess{N}_M{4 * N * N}_heun2", steps, warmup)
 
 
 def main():
@@ -153,6 +169,9 @@ def main():
                     help="arrival rate as a fraction of the one-at-a-time capacity")
     ap.add_argument("--cavity-steps", type=int, default=40,
                     help="Heun steps timed on the full-size walled cavity, 1300^2 x 512 ordinates (0 skips it)")
+    ap.add_argument("--tess-steps", type=int, default=10,
+                    help="Heun steps timed on the 700^2 lattice with the tessellation quadrature, "
+                         "N = 22 (1936 ordinates; 0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -241,6 +260,8 @@ def main():
         del src, dst
     if args.cavity_steps:
         line["cavity"] = time_cavity(args.cavity_steps, args.dtype)
+    if args.tess_steps:
+        line["tessellation"] = time_tessellation(args.tess_steps, args.dtype)
     from paper_2505_17284_amd import serve
 
     if args.uq:

@@ -39,6 +39,9 @@ extern "C" {
 #define SN_MAX_TALLIES 8   /* absorption tally regions */
 #define SN_MAX_RECTS 4     /* outflow/inflow rectangles */
 #define SN_MAX_FLUENCE_BLOCKS 1024 /* blocks of sn_plan_fluence_functionals */
+#define SN_MAX_PROBES 16             /* space-time probes */
+#define SN_MAX_WINDOWS 4096          /* time windows of the probes */
+#define SN_MAX_PROBE_CELLS (1 << 20) /* cells of all probes together */
 #define SN_MAX_REGIONS 256 /* material regions (uint8 ids) */
 #define SN_MAX_ORDINATES 4096
 
@@ -63,6 +66,13 @@ typedef int32_t sn_status;
 #define SN_F32 0  /* psi stored as IEEE binary32 */
 #define SN_BF16 1 /* psi stored as bfloat16 (round to nearest even), math in FP32 */
 
+/* One cell of a space-time probe (see sn_problem). */
+typedef struct sn_probe_cell {
+    int32_t cell;  /* interior index j * nx + i */
+    int32_t probe; /* 0 .. n_probes-1 */
+    double weight; /* the cell's share of the probe's average */
+} sn_probe_cell;
+
 /* A problem statement (Sec. 4.1 with the benchmark data of Sec. 3).
  *
  *  nx, ny, h      grid of nx * ny square cells of side h > 0; cell (i, j),
@@ -86,6 +96,19 @@ typedef int32_t sn_status;
  *                 0 <= i0 < i1 <= nx, 0 <= j0 < j1 <= ny; the outflow and
  *                 inflow through each rectangle's boundary are QoIs.
  *  psi_dtype      SN_F32 or SN_BF16.
+ *  n_probes, n_windows, n_probe_cells, probe_cells
+ *                 space-time probes (Hohlraum QoI-1, Sec. 3.2.1): probe p
+ *                 averages phi = sum_k w_k psi_k, J_x = sum_k w_k xi_k psi_k and
+ *                 J_y = sum_k w_k eta_k psi_k over its cells, weighted by
+ *                 probe_cells[].weight (the cell's share of the probe region,
+ *                 e.g. area inside a ball over the ball's area), and over each
+ *                 of n_windows equal windows of [0, t_end]: the time integral
+ *                 (the stepper's rule) divided by the window's length. A step
+ *                 counts in the window holding its start time, floor(step *
+ *                 n_windows / N_t); steps past N_t count nowhere.
+ *                 0 <= n_probes <= SN_MAX_PROBES; 1 <= n_windows <=
+ *                 SN_MAX_WINDOWS when n_probes > 0; probe_cells[n_probe_cells]
+ *                 (n_probe_cells <= SN_MAX_PROBE_CELLS) may be NULL when 0.
  *  fluence        1: also accumulate the fluence Phi = int_0^t phi dt per cell
  *                 in FP64, with the stepper's time rule (Euler dt phi(psi^n);
  *                 Heun dt/2 (phi(psi^n) + phi(psi^(1)))); the Hohlraum QoI-3
@@ -113,6 +136,8 @@ typedef struct sn_problem {
     const int32_t *rects;
     int32_t psi_dtype;
     int32_t fluence;
+    int32_t n_probes, n_windows, n_probe_cells;
+    const struct sn_probe_cell *probe_cells;
 } sn_problem;
 
 /* Sizes and derived constants of a plan. psi_bytes is the size of ONE angular
@@ -214,6 +239,13 @@ sn_status sn_plan_read_psi(const sn_plan *plan, float *host_out, void *stream);
 /* Copy the current scalar flux phi = sum_k w_k psi_k to host [ny][nx]
  * float32 (the FP32 value the next stage uses). Synchronises `stream`. */
 sn_status sn_plan_read_phi(const sn_plan *plan, float *host_out, void *stream);
+
+/* Copy the probes' window averages (sn_problem.n_probes) accumulated since
+ * sn_plan_init to host [n_windows][n_probes][3] float64 = (phi, J_x, J_y);
+ * windows not reached yet hold their partial integral over the window's
+ * full length. Synchronises `stream`. SN_ERR_STATE if the plan has no
+ * probes. */
+sn_status sn_plan_read_probes(const sn_plan *plan, double *host_out, void *stream);
 
 /* Copy the fluence Phi (sn_problem.fluence) accumulated since sn_plan_init
  * to host [ny][nx] float64. Synchronises `stream`. SN_ERR_STATE if the plan

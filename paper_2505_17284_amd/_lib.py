@@ -29,12 +29,16 @@ MAX_RECTS = 4
 MAX_FLUENCE_BLOCKS = 1024
 # sn_fluence_piece: two interior cell indices and the piece's weight
 FLUENCE_PIECE = np.dtype([("cell_a", np.int32), ("cell_b", np.int32), ("weight", np.float64)])
+# sn_probe_cell: interior cell index, probe id, the cell's weight in the probe's average
+PROBE_CELL = np.dtype([("cell", np.int32), ("probe", np.int32), ("weight", np.float64)])
+MAX_PROBES = 16
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = [
     "sn_plan_create", "sn_plan_create_tuned", "sn_plan_create_shaped", "sn_plan_get_info", "sn_plan_bind",
     "sn_plan_init", "sn_plan_run", "sn_plan_run_unbounded", "sn_plan_qoi",
     "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_read_fluence", "sn_plan_fluence_functionals",
+    "sn_plan_read_probes",
     "sn_plan_use_graph", "sn_plan_set_timing",
     "sn_plan_kernel_ms", "sn_plan_destroy", "sn_status_str", "sn_last_error",
     "sn_batch_workspace_bytes", "sn_batch_create", "sn_plan_footprint", "sn_batch_admit", "sn_batch_run",
@@ -54,6 +58,7 @@ class SnProblem(ctypes.Structure):
         ("tally", _vp), ("n_tallies", _i32), ("bc", _i32 * 4), ("inflow", _d * 4),
         ("order", _i32), ("stepper", _i32), ("cfl", _d), ("t_end", _d),
         ("n_rects", _i32), ("rects", _vp), ("psi_dtype", _i32), ("fluence", _i32),
+        ("n_probes", _i32), ("n_windows", _i32), ("n_probe_cells", _i32), ("probe_cells", _vp),
     ]
 
 
@@ -129,6 +134,7 @@ def lib():
         L.sn_plan_read_psi.argtypes = [_vp, _vp, _vp]
         L.sn_plan_read_phi.argtypes = [_vp, _vp, _vp]
         L.sn_plan_read_fluence.argtypes = [_vp, _vp, _vp]
+        L.sn_plan_read_probes.argtypes = [_vp, _vp, _vp]
         L.sn_plan_fluence_functionals.argtypes = [_vp, _vp, _i32, _vp, _i32, _vp, _vp]
         L.sn_plan_use_graph.argtypes = [_vp, _i32]
         L.sn_plan_set_timing.argtypes = [_vp, _i32]
@@ -166,7 +172,9 @@ def check(status: int, where: str):
 class MarshalledProblem:
     """A problem statement laid out as the C struct, owning contiguous copies."""
 
-    def __init__(self, p, fluence: bool = False):
+    def __init__(self, p, fluence: bool = False, probes=None):
+        """probes: None, or a dict with n_probes, n_windows and cells (an array
+        of PROBE_CELL records)."""
         qd = p.quad
         self.keep = dict(
             xi=np.ascontiguousarray(qd.xi, np.float64), eta=np.ascontiguousarray(qd.eta, np.float64),
@@ -194,4 +202,10 @@ class MarshalledProblem:
         s.n_rects = int(k["rects"].shape[0])
         s.psi_dtype = SN_BF16 if p.psi_dtype == "bf16" else SN_F32
         s.fluence = 1 if fluence else 0
+        if probes is not None:
+            cells = np.ascontiguousarray(probes["cells"], dtype=PROBE_CELL)
+            self.keep["probe_cells"] = cells
+            s.n_probes, s.n_windows = int(probes["n_probes"]), int(probes["n_windows"])
+            s.n_probe_cells = int(cells.shape[0])
+            s.probe_cells = cells.ctypes.data if cells.shape[0] else None
         self.struct = s

@@ -87,11 +87,65 @@ __global__ void __launch_bounds__(256) sn_ghost_fill_kernel(const GhostArgs a) {
 // fixed order (deterministic), scales, and accumulates the time integral.
 // Workgroups [nq, nq + n_phi_wg): phi = sum over groups of the stage's
 // partial scalar fluxes, in group order, for every interior cell (4 padded
-// columns per thread, ny * pitch / 4 threads).
+// columns per thread, ny * pitch / 4 threads), first adding the replaced phi
+// (the stage input's) to the fluence when that is kept. Workgroups
+// [nq + n_phi_wg, + n_probes): one per space-time probe.
 using FArgs = const __attribute__((address_space(4))) FinalizeArgs&;
 using FArgsPtr = const __attribute__((address_space(4))) FinalizeArgs*;
 
+__device__ double block_sum(double v, double* red) {
+    __syncthreads();  // red may still be read by the previous reduction
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Probe p: phi, J_x, J_y of the stage input over the probe's weighted cells,
+// added with the stage's time weight to the window the step falls in. Each
+// probe block owns its step counter, so reading and advancing it need no
+// coordination with other blocks.
+__device__ void probe_block(FArgs a, int p) {
+    __shared__ double red[256];
+    const int32_t step = a.pstep[p];
+    __syncthreads();  // every thread has read the counter before thread 0 advances it
+    const int64_t w = (int64_t)step * a.n_windows / a.nt;
+    if (w < a.n_windows) {
+        const int c0 = a.pstart[p], nc = a.pstart[p + 1] - c0;
+        const int M = a.M;
+        double m0 = 0.0, mx = 0.0, my = 0.0;
+        for (int64_t u = threadIdx.x; u < (int64_t)nc * M; u += 256) {
+            const int c = (int)(u / M), k = (int)(u - (int64_t)c * M);
+            const ProbeCell pc = a.pcell[c0 + c];
+            const int64_t e = (int64_t)k * a.plane + pc.off;
+            const float x = a.dtype == 0 ? static_cast<const float*>(a.psi_in)[e]
+                                         : bf16_widen(static_cast<const uint16_t*>(a.psi_in)[e]);
+            const double v = pc.weight * (double)x;
+            m0 += a.pmom[3 * k] * v;
+            mx += a.pmom[3 * k + 1] * v;
+            my += a.pmom[3 * k + 2] * v;
+        }
+        const double s0 = block_sum(m0, red);
+        const double sx = block_sum(mx, red);
+        const double sy = block_sum(my, red);
+        if (threadIdx.x == 0) {
+            double* acc = a.pacc + (w * a.n_probes + p) * 3;
+            acc[0] += a.pcoef * s0;
+            acc[1] += a.pcoef * sx;
+            acc[2] += a.pcoef * sy;
+        }
+    }
+    if (threadIdx.x == 0 && a.last_stage) a.pstep[p] = step + 1;
+}
+
 __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
+    if (blk >= a.nq + a.n_phi_wg) {
+        probe_block(a, blk - a.nq - a.n_phi_wg);
+        return;
+    }
     if (blk >= a.nq) {
         // four consecutive padded columns per thread (16-byte aligned: the
         // pitch is a multiple of 16 elements); only interior cells are written
@@ -203,17 +257,6 @@ __global__ void __launch_bounds__(256) sn_phi_init_kernel(const PhiInitArgs a) {
 // One workgroup, FP64 throughout, fixed reduction order. The value of a piece
 // is the mean of sigma_a * fluence over its two cells; every set's weighted
 // sum is a strided partial per thread followed by a tree over the workgroup.
-__device__ double fl_block_sum(double v, double* red) {
-    __syncthreads();  // red may still be read by the previous reduction
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int m = 128; m >= 1; m >>= 1) {
-        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
-        __syncthreads();
-    }
-    return red[0];
-}
-
 __device__ __forceinline__ double fl_cell(const FluenceArgs& a, int32_t c) {
     const int32_t j = c / a.nx, i = c - j * a.nx;
     return a.sa[a.region[a.origin + (int64_t)j * a.pitch + i]] * a.fluence[c];
@@ -248,7 +291,7 @@ __global__ void __launch_bounds__(256) sn_fluence_functionals_kernel(const Fluen
             const FluencePiece q = a.pieces[p];
             v += q.w * (0.5 * (fl_cell(a, q.a) + fl_cell(a, q.b)));
         }
-        const double tot = fl_block_sum(v, red);
+        const double tot = block_sum(v, red);
         if (threadIdx.x == 0) setsum[g] = tot;
     }
     __syncthreads();
@@ -264,7 +307,7 @@ __global__ void __launch_bounds__(256) sn_fluence_functionals_kernel(const Fluen
         const double d = A_L - 0.5 * (fl_cell(a, q.a) + fl_cell(a, q.b));
         v += q.w * d * d;
     }
-    const double V_L = fl_block_sum(v, red);
+    const double V_L = block_sum(v, red);
     if (threadIdx.x == 0) {
         a.out[0] = A_G;
         a.out[1] = V_G;
@@ -305,7 +348,7 @@ hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq + a.n_phi_wg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq + a.n_phi_wg + a.n_probes), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

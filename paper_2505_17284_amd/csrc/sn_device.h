@@ -30,6 +30,7 @@ constexpr int kMaxTallies = 8;
 constexpr int kMaxRects = 4;
 constexpr int kMaxQ = 1 + kMaxTallies + 2 * kMaxRects;  // mass, absorption, out, in
 constexpr int kMaxFluenceBlocks = 1024;
+constexpr int kMaxProbes = 16;
 
 enum StageMode : int {
     kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)                   (Euler, Heun stage 1)
@@ -130,6 +131,23 @@ struct FinalizeArgs {
     double coef;            // weight of this stage in the time integral
     int32_t n_wg, nq;
     double* fluence;        // [ny][nx] running time integral of phi, or NULL
+    // space-time probes: blocks [nq + n_phi_wg, + n_probes) each reduce one
+    // probe's moments of the stage input into its current time window
+    const void* psi_in;     // the stage input (dtype below), padded planes
+    const struct ProbeCell* pcell;  // [cells] sorted by probe
+    const int32_t* pstart;  // [n_probes + 1]
+    const double* pmom;     // [M][3] w, w xi, w eta in FP64
+    double* pacc;           // [n_windows][n_probes][3]
+    int32_t* pstep;         // [n_probes] steps finished so far (one counter per probe block)
+    double pcoef;           // coef / window length
+    int32_t n_probes;       // 0: no probe blocks in this launch
+    int32_t n_windows, nt, M, dtype;
+    int32_t last_stage;     // 1: this stage ends a step
+};
+
+struct ProbeCell {
+    int64_t off;  // the cell's offset in a padded plane
+    double weight;
 };
 
 // One piece of a block or line integral of sigma_a * fluence (the layout of

@@ -200,9 +200,10 @@ sn_status sn_batch_admit(sn_batch* B, sn_plan* P, int32_t* slot) {
         sa[0] = stage_args(P, P->psi[0], nullptr, P->psi[1]);
         sa[1] = stage_args(P, P->psi[1], nullptr, P->psi[0]);
     }
+    // one finalize per stage-argument variant (it reads that variant's input)
     FinalizeArgs fa[2];
-    fa[0] = finalize_args(P, P->stepper == SN_HEUN ? 1 : 0);
-    fa[1] = finalize_args(P, P->stepper == SN_HEUN ? 2 : 0);
+    fa[0] = finalize_args(P, P->stepper == SN_HEUN ? 1 : 0, P->psi[0]);
+    fa[1] = finalize_args(P, P->stepper == SN_HEUN ? 2 : 0, P->psi[1]);
     HIP_TRY(hipMemcpy(B->ws + B->off_stage + (size_t)s * 2 * sizeof(StageArgs), sa, sizeof sa, hipMemcpyHostToDevice),
             "upload stage arguments");
     HIP_TRY(hipMemcpy(B->ws + B->off_final + (size_t)s * 2 * sizeof(FinalizeArgs), fa, sizeof fa, hipMemcpyHostToDevice),
@@ -300,11 +301,11 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
                         // the averaging stage has a layout (groups, workgroups) of its own
                         const int layout = (P->stepper == SN_HEUN && st == 1) ? 1 : 0;
                         sel.push_back(2 * i + variant);
-                        fsel.push_back(2 * i + layout);
+                        fsel.push_back(2 * i + variant);
                         first.push_back(r.total);
                         ffirst.push_back(r.ftotal);
                         r.total += P->n_wg_l[layout];
-                        r.ftotal += P->nq + (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
+                        r.ftotal += finalize_workgroups(P, P->stepper == SN_HEUN ? 1 + st : 0);
                     }
                     r.n = (int32_t)sel.size();
                     first.push_back(r.total);

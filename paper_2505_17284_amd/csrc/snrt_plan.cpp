@@ -65,6 +65,24 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     if (p->stepper != SN_EULER && p->stepper != SN_HEUN) return fail(SN_ERR_INVALID, "stepper must be Euler or Heun");
     if (p->psi_dtype != SN_F32 && p->psi_dtype != SN_BF16) return fail(SN_ERR_INVALID, "psi_dtype must be F32 or BF16");
     if (p->fluence != 0 && p->fluence != 1) return fail(SN_ERR_INVALID, "fluence must be 0 or 1");
+    if (p->n_probes < 0 || p->n_probes > SN_MAX_PROBES)
+        return fail(SN_ERR_INVALID, "n_probes = %d out of range [0, %d]", p->n_probes, SN_MAX_PROBES);
+    if (p->n_probes > 0) {
+        if (p->n_windows < 1 || p->n_windows > SN_MAX_WINDOWS)
+            return fail(SN_ERR_INVALID, "n_windows = %d out of range [1, %d]", p->n_windows, SN_MAX_WINDOWS);
+        if (p->n_probe_cells < 0 || p->n_probe_cells > SN_MAX_PROBE_CELLS)
+            return fail(SN_ERR_INVALID, "n_probe_cells = %d out of range [0, %d]", p->n_probe_cells,
+                        SN_MAX_PROBE_CELLS);
+        if (p->n_probe_cells > 0 && !p->probe_cells) return fail(SN_ERR_INVALID, "probe_cells is NULL");
+        for (int c = 0; c < p->n_probe_cells; ++c) {
+            const sn_probe_cell& pc = p->probe_cells[c];
+            if (pc.cell < 0 || (int64_t)pc.cell >= (int64_t)p->nx * p->ny)
+                return fail(SN_ERR_INVALID, "probe cell %d: cell index %d out of range", c, pc.cell);
+            if (pc.probe < 0 || pc.probe >= p->n_probes)
+                return fail(SN_ERR_INVALID, "probe cell %d: probe %d out of range", c, pc.probe);
+            if (!std::isfinite(pc.weight)) return fail(SN_ERR_INVALID, "probe cell %d: weight not finite", c);
+        }
+    }
     if (p->fluence && (int64_t)p->nx * p->ny > 0x7fffffff)
         return fail(SN_ERR_UNSUPPORTED, "fluence needs nx * ny < 2^31 (cell indices are 32-bit)");
     if (!(p->cfl > 0) || !std::isfinite(p->cfl)) return fail(SN_ERR_INVALID, "cfl must be finite and > 0");
@@ -157,6 +175,22 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     P->stepper = p->stepper;
     P->dtype = p->psi_dtype;
     P->fluence = p->fluence == 1;
+    P->n_probes = p->n_probes;
+    P->n_windows = p->n_probes > 0 ? p->n_windows : 0;
+    P->pcell_h.clear();
+    P->pstart_h.assign(P->n_probes + 1, 0);
+    if (P->n_probes > 0) {
+        // cells grouped by probe, in the caller's order within a probe; `off`
+        // holds the interior index here and becomes the padded-plane offset
+        // when the tables are uploaded
+        for (int q = 0; q < P->n_probes; ++q) {
+            P->pstart_h[q] = (int32_t)P->pcell_h.size();
+            for (int c = 0; c < p->n_probe_cells; ++c)
+                if (p->probe_cells[c].probe == q)
+                    P->pcell_h.push_back(ProbeCell{(int64_t)p->probe_cells[c].cell, p->probe_cells[c].weight});
+        }
+        P->pstart_h[P->n_probes] = (int32_t)P->pcell_h.size();
+    }
     P->cfl = p->cfl;
     P->t_end = p->t_end;
     return SN_OK;
@@ -258,6 +292,23 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     off += align256(sizeof(int32_t));
     P->off_fluence = off;
     if (P->fluence) off += align256((size_t)P->nx * P->ny * sizeof(double));
+    P->off_pcell = off;
+    P->off_pstart = off;
+    P->off_pmom = off;
+    P->off_pacc = off;
+    P->off_pstep = off;
+    if (P->n_probes > 0) {
+        P->off_pcell = off;
+        off += align256(P->pcell_h.size() * sizeof(ProbeCell));
+        P->off_pstart = off;
+        off += align256((size_t)(P->n_probes + 1) * sizeof(int32_t));
+        P->off_pmom = off;
+        off += align256((size_t)P->M * 3 * sizeof(double));
+        P->off_pacc = off;
+        off += align256((size_t)P->n_windows * P->n_probes * 3 * sizeof(double));
+        P->off_pstep = off;
+        off += align256((size_t)P->n_probes * sizeof(int32_t));
+    }
     P->scratch_bytes = off;
 
     // Tables, computed in FP64 and rounded once.
@@ -281,6 +332,12 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
         c.cq = (float)(P->dt * P->q[r]);
         c.tally = P->tally[r];
         c.sa = P->sa[r];
+    }
+    P->pmom_h.assign((size_t)P->M * 3, 0.0);
+    for (int k = 0; k < P->M; ++k) {
+        P->pmom_h[3 * k] = P->w[k];
+        P->pmom_h[3 * k + 1] = P->w[k] * P->xi[k];
+        P->pmom_h[3 * k + 2] = P->w[k] * P->eta[k];
     }
     P->region_h.assign((size_t)P->plane, 0);
     for (int j = 0; j < P->ny; ++j)
@@ -333,7 +390,12 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
     return a;
 }
 
-FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
+int snh::finalize_workgroups(const sn_plan* P, int kind) {
+    const int phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
+    return P->nq + phi_wg + (kind < 0 ? 0 : P->n_probes);
+}
+
+FinalizeArgs snh::finalize_args(const sn_plan* P, int kind, const char* psi_in) {
     const int l = kind == 2 ? 1 : 0;  // layout of the stage just run
     FinalizeArgs f{};
     f.phi_part = P->sp<float>(P->off_phi_part);
@@ -355,6 +417,21 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.n_wg = P->n_wg_l[l];
     f.nq = P->nq;
     f.fluence = P->fluence ? P->sp<double>(P->off_fluence) : nullptr;
+    f.n_probes = kind < 0 ? 0 : P->n_probes;
+    if (P->n_probes > 0) {
+        f.psi_in = psi_in;
+        f.pcell = P->sp<ProbeCell>(P->off_pcell);
+        f.pstart = P->sp<int32_t>(P->off_pstart);
+        f.pmom = P->sp<double>(P->off_pmom);
+        f.pacc = P->sp<double>(P->off_pacc);
+        f.pstep = P->sp<int32_t>(P->off_pstep);
+        f.pcoef = f.coef / (P->t_end / P->n_windows);
+        f.n_windows = P->n_windows;
+        f.nt = P->nt;
+        f.M = P->M;
+        f.dtype = P->dtype;
+        f.last_stage = kind == 0 || kind == 2 ? 1 : 0;
+    }
     return f;
 }
 
@@ -417,7 +494,7 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
         P->ev_kind[P->ev_used] = kind;
         P->ev_used++;
     }
-    const FinalizeArgs f = finalize_args(P, kind);
+    const FinalizeArgs f = finalize_args(P, kind, in);
     HIP_TRY(launch_finalize(f, s), "finalize launch");
     return SN_OK;
 }
@@ -601,6 +678,26 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     if (P->fluence)
         HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_fluence), 0, (size_t)P->nx * P->ny * sizeof(double), s),
                 "clear fluence");
+    if (P->n_probes > 0) {
+        std::vector<ProbeCell> pc(P->pcell_h);
+        for (ProbeCell& c : pc) {
+            const int64_t j = c.off / P->nx, i = c.off - j * P->nx;
+            c.off = P->origin + j * P->pitch + i;
+        }
+        if (!pc.empty())
+            HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pcell), pc.data(), pc.size() * sizeof(ProbeCell),
+                                   hipMemcpyHostToDevice, s), "upload probe cells");
+        HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pstart), P->pstart_h.data(), P->pstart_h.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s), "upload probe starts");
+        HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pmom), P->pmom_h.data(), P->pmom_h.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s), "upload probe moments");
+        HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_pacc), 0,
+                               (size_t)P->n_windows * P->n_probes * 3 * sizeof(double), s), "clear probe windows");
+        HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_pstep), 0, (size_t)P->n_probes * sizeof(int32_t), s),
+                "clear probe steps");
+        // the host copy above must outlive the asynchronous upload
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
     HIP_TRY(hipMemsetAsync(P->psi[0], 0, P->psi_bytes, s), "clear psi A");
     HIP_TRY(hipMemsetAsync(P->psi[1], 0, P->psi_bytes, s), "clear psi B");
     P->cur = 0;
@@ -759,6 +856,17 @@ sn_status sn_plan_read_phi(const sn_plan* P, float* host_out, void* stream) {
     HIP_TRY(hipMemcpy2DAsync(host_out, P->nx * sizeof(float), P->sp<char>(P->off_phi) + P->origin * sizeof(float),
                              P->pitch * sizeof(float),
                              P->nx * sizeof(float), P->ny, hipMemcpyDeviceToHost, s), "read phi");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return SN_OK;
+}
+
+sn_status sn_plan_read_probes(const sn_plan* P, double* host_out, void* stream) {
+    if (!P || !host_out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!P->bound || !P->inited) return fail(SN_ERR_STATE, "plan not bound and initialised");
+    if (P->n_probes == 0) return fail(SN_ERR_STATE, "plan has no probes");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(host_out, P->sp<char>(P->off_pacc), (size_t)P->n_windows * P->n_probes * 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, s), "read probes");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     return SN_OK;
 }

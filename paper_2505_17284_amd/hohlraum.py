@@ -1,4 +1,11 @@
-"""Green-band QoIs of the Hohlraum benchmark (Sec. 3.2.1, QoI-3 to QoI-6).
+"""Hohlraum QoIs laid out on the host (Sec. 3.2.1): the QoI-1 probes and the
+green-band QoI-3 to QoI-6.
+
+QoI-1 averages phi, J_x and J_y over a ball of radius 0.01 around each of
+four points and over each tenth of [0, T]. ``probe_cells`` gives every cell
+of each ball its weight, the exact area of the cell inside the ball over the
+ball's area; the plan accumulates the windows on the device (``Plan(...,
+probes=probe_cells(problem))``, ``Plan.probes()``).
 
 All four are functionals of a = sigma_a * Phi, with Phi the fluence (time
 integral of the scalar flux) that a plan made with ``fluence=True``
@@ -24,7 +31,7 @@ import math
 
 import numpy as np
 
-from ._lib import FLUENCE_PIECE
+from ._lib import FLUENCE_PIECE, PROBE_CELL
 
 BLOCK = 0.05
 # walk of the block centres: start, then (step direction, steps) per side
@@ -115,4 +122,70 @@ def green_band_qois(plan) -> dict:
     return plan.fluence_functionals(pieces, starts, nb)
 
 
-__all__ = ["block_centres", "green_band_pieces", "green_band_qois"]
+PROBE_CENTRES = ((-0.4, 0.0), (0.4, 0.0), (0.0, -0.5), (0.0, 0.5))
+PROBE_RADIUS = 0.01
+PROBE_WINDOWS = 10
+
+
+def _disc_below(x: float, y: float, r: float) -> float:
+    """Area of the disc of radius r about the origin with X <= x and Y <= y.
+
+    The disc's column at X = t spans |Y| <= s(t) = sqrt(r^2 - t^2); below
+    the line Y = y it holds min(y, s) + s when that is positive. With
+    a = sqrt(r^2 - y^2) that is 2s for |t| >= a and y + s for |t| < a when
+    y >= 0, and y + s for |t| < a (nothing elsewhere) when y < 0. The
+    integral of s is S(t) = (t s(t) + r^2 asin(t / r)) / 2.
+    """
+    if y <= -r or x <= -r:
+        return 0.0
+    x = min(x, r)
+
+    def S(t):
+        return 0.5 * (t * math.sqrt(max(r * r - t * t, 0.0)) + r * r * math.asin(max(-1.0, min(1.0, t / r))))
+
+    if y >= r:
+        return 2.0 * (S(x) - S(-r))
+    a = math.sqrt(r * r - y * y)
+    total = 0.0
+    # middle band |t| < a: y + s
+    lo, hi = -a, min(x, a)
+    if hi > lo:
+        total += y * (hi - lo) + S(hi) - S(lo)
+    if y >= 0:  # outer bands |t| >= a: 2 s
+        hi = min(x, -a)
+        if hi > -r:
+            total += 2.0 * (S(hi) - S(-r))
+        if x > a:
+            total += 2.0 * (S(x) - S(a))
+    return total
+
+
+def disc_rect_area(cx, cy, r, x0, x1, y0, y1) -> float:
+    """Exact area of the disc about (cx, cy) inside [x0, x1] x [y0, y1]."""
+    def q(x, y):
+        return _disc_below(x - cx, y - cy, r)
+
+    return max(0.0, q(x1, y1) - q(x0, y1) - q(x1, y0) + q(x0, y0))
+
+
+def probe_cells(problem, centres=PROBE_CENTRES, r: float = PROBE_RADIUS, n_windows: int = PROBE_WINDOWS) -> dict:
+    """The probes as ``Plan(..., probes=...)`` takes them: every cell meeting a
+    ball with weight (area inside the ball) / (pi r^2)."""
+    nx, ny, h = problem.nx, problem.ny, problem.h
+    recs = []
+    for q, (cx, cy) in enumerate(centres):
+        i0 = max(0, int(math.floor((cx - r - problem.x0) / h)))
+        i1 = min(nx, int(math.ceil((cx + r - problem.x0) / h)))
+        j0 = max(0, int(math.floor((cy - r - problem.y0) / h)))
+        j1 = min(ny, int(math.ceil((cy + r - problem.y0) / h)))
+        for j in range(j0, j1):
+            for i in range(i0, i1):
+                xa, ya = problem.x0 + i * h, problem.y0 + j * h
+                area = disc_rect_area(cx, cy, r, xa, xa + h, ya, ya + h)
+                if area > _EPS * h * h:
+                    recs.append((j * nx + i, q, area / (math.pi * r * r)))
+    cells = np.array(recs, dtype=PROBE_CELL)
+    return dict(n_probes=len(centres), n_windows=n_windows, cells=cells)
+
+
+__all__ = ["block_centres", "green_band_pieces", "green_band_qois", "probe_cells", "disc_rect_area"]

@@ -178,6 +178,59 @@ def product_quadrature(n_polar: int, n_azim: int, half_range: bool = False) -> Q
                       mirror_y=mirror_y, n_polar=n_polar, n_azim=n_azim)
 
 
+def tessellation_quadrature(N: int) -> Quadrature:
+    """The tessellation rule of Sec. 5.1.1: M = 4 N^2 ordinates on S^2_+.
+
+    Each face of the octahedron with vertices on the unit sphere is cut into
+    N^2 triangles by the lines parallel to its edges through the points that
+    divide the edges into N parts. An ordinate is the centroid of one such
+    planar triangle pushed out to the unit sphere; its weight is the area of
+    the spherical triangle spanned by the pushed-out vertices (its spherical
+    excess E, from tan(E/2) = |a . (b x c)| / (1 + a.b + b.c + c.a)). The
+    weights tile the hemisphere, so they sum to 2 pi.
+
+    The face in the first octant is computed; the other three faces of the
+    upper hemisphere are its images under xi -> -xi and eta -> -eta, so mirror
+    partners are exact. Order: k = f N^2 + t, faces f = (+,+), (-,+), (-,-),
+    (+,-) in (xi, eta), triangles t of the first face as generated.
+    """
+    if N < 1:
+        raise ValueError("need N >= 1")
+
+    def node(i, j):  # barycentric grid point of the face x + y + z = 1
+        return np.array([i / N, j / N, (N - i - j) / N])
+
+    tris = []
+    for i in range(N):
+        for j in range(N - i):
+            tris.append((node(i, j), node(i + 1, j), node(i, j + 1)))
+            if i + j <= N - 2:
+                tris.append((node(i + 1, j), node(i + 1, j + 1), node(i, j + 1)))
+    n1 = len(tris)
+    pts = np.empty((n1, 3))
+    wts = np.empty(n1)
+    for t, (a, b, c) in enumerate(tris):
+        g = (a + b + c) / 3.0
+        pts[t] = g / np.linalg.norm(g)
+        ua, ub, uc = (v / np.linalg.norm(v) for v in (a, b, c))
+        num = abs(np.dot(ua, np.cross(ub, uc)))
+        den = 1.0 + np.dot(ua, ub) + np.dot(ub, uc) + np.dot(uc, ua)
+        wts[t] = 2.0 * np.arctan2(num, den)
+    sx = np.array([1.0, -1.0, -1.0, 1.0])
+    sy = np.array([1.0, 1.0, -1.0, -1.0])
+    xi = (sx[:, None] * pts[None, :, 0]).reshape(-1)
+    eta = (sy[:, None] * pts[None, :, 1]).reshape(-1)
+    mu = np.tile(pts[:, 2], 4)
+    w = np.tile(wts, 4)
+    t = np.arange(n1)
+    fx = np.array([1, 0, 3, 2])  # face of the xi-mirror
+    fy = np.array([3, 2, 1, 0])  # face of the eta-mirror
+    mirror_x = (fx[:, None] * n1 + t[None, :]).reshape(-1).astype(np.int32)
+    mirror_y = (fy[:, None] * n1 + t[None, :]).reshape(-1).astype(np.int32)
+    return Quadrature(mu=mu, xi=xi, eta=eta, w=w, mirror_x=mirror_x, mirror_y=mirror_y,
+                      n_polar=N, n_azim=0)
+
+
 def quadrature_for(M: int) -> Quadrature:
     if M not in M_SPLIT:
         raise ValueError(f"no product split registered for M={M}")

@@ -26,10 +26,10 @@ def _torch():
 
 
 def plan_info(problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
-              group_size_average: int = 0, fluence: bool = False) -> dict:
+              group_size_average: int = 0, fluence: bool = False, probes=None) -> dict:
     """Derived constants and buffer sizes of a plan (host only, no GPU).
     group_size applies to both stages unless group_size_average is given."""
-    m = MarshalledProblem(problem, fluence)
+    m = MarshalledProblem(problem, fluence, probes)
     h = ctypes.c_void_p()
     check(lib().sn_plan_create_shaped(ctypes.byref(m.struct), group_size, group_size_average or group_size,
                                       rows_per_wave, waves_per_group, ctypes.byref(h)), "sn_plan_create")
@@ -62,12 +62,16 @@ class Plan:
 
     def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
                  device: str = "cuda:0", psi0=None, graph_steps: int = 0, group_size_average: int = 0,
-                 fluence: bool = False):
+                 fluence: bool = False, probes=None):
+        """fluence: keep the time integral of phi per cell (``fluence()``);
+        probes: space-time probes, a dict with n_probes, n_windows and cells
+        (PROBE_CELL records; ``hohlraum.probe_cells`` builds the paper's)."""
         torch = _torch()
         assert problem.n_tallies <= MAX_TALLIES and problem.n_rects <= MAX_RECTS
         self.problem = problem
         self.device = torch.device(device)
-        self._m = MarshalledProblem(problem, fluence)
+        self._probes = probes
+        self._m = MarshalledProblem(problem, fluence, probes)
         self.h = ctypes.c_void_p()
         check(lib().sn_plan_create_shaped(ctypes.byref(self._m.struct), group_size,
                                           group_size_average or group_size, rows_per_wave,
@@ -130,6 +134,14 @@ class Plan:
         p = self.problem
         out = np.empty((p.ny, p.nx), dtype=np.float32)
         check(lib().sn_plan_read_phi(self.h, out.ctypes.data, self.stream), "sn_plan_read_phi")
+        return out
+
+    def probes(self) -> np.ndarray:
+        """Window averages of the probes so far: [n_windows][n_probes][phi, J_x, J_y]."""
+        if self._probes is None:
+            raise SnError(7, "sn_plan_read_probes", "plan has no probes")
+        out = np.empty((int(self._probes["n_windows"]), int(self._probes["n_probes"]), 3), dtype=np.float64)
+        check(lib().sn_plan_read_probes(self.h, out.ctypes.data, self.stream), "sn_plan_read_probes")
         return out
 
     def fluence(self) -> np.ndarray:

@@ -7,7 +7,7 @@ value here comes from the HIP path.
     python tests/golden/make_oracle_goldens.py hohlraum260  # ~2 min on 8 cores
 
 Hohlraum cases also store the green-band QoI-3 to QoI-6 of the oracle's
-fluence (oracle/hohlraum_qoi.py).
+fluence and the QoI-1 probe windows (oracle/hohlraum_qoi.py).
 """
 
 import json
@@ -38,7 +38,7 @@ def main(names):
         p = make()
         t0 = time.time()
         hohl = p.meta.get("kind") == "hohlraum"
-        r = oracle.solve(p, fluence=hohl)
+        r = oracle.solve(p, fluence=hohl, probes=hohlraum_qoi.probe_cells(p) if hohl else None)
         out = dict(
             problem=p.name, nx=p.nx, ny=p.ny, M=p.M, order=p.order, stepper=p.stepper,
             nt=r["nt"], dt=r["dt"], t=r["t"],
@@ -52,6 +52,7 @@ def main(names):
             band = hohlraum_qoi.qois(p, r["fluence"])
             out["green_band"] = {k: float(band[k]) for k in ("A_G", "V_G", "A_L", "V_L", "length")}
             out["green_band"]["A"] = [float(a) for a in band["A"]]
+            out["probes"] = r["probes"].tolist()  # [window][probe][phi, J_x, J_y]
         with open(os.path.join(HERE, fname), "w") as f:
             json.dump(out, f, indent=1)
         print(name, "done in", round(out["oracle_seconds"], 1), "s", flush=True)

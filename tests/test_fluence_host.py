@@ -45,3 +45,34 @@ def test_pieces_reproduce_oracle_qois(n):
     np.testing.assert_allclose(got["A"], want["A"], rtol=1e-12)
     for k in ("A_G", "V_G", "A_L", "V_L"):
         assert got[k] == pytest.approx(want[k], rel=1e-11), k
+
+
+def test_disc_areas_match_the_oracle_quadrature():
+    import math
+    import random
+
+    from oracle import hohlraum_qoi
+
+    rng = random.Random(5)
+    for _ in range(500):
+        cx, cy, r = rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.05, 1)
+        x0, y0 = rng.uniform(-1.5, 1.5), rng.uniform(-1.5, 1.5)
+        w, h = rng.uniform(0.01, 1), rng.uniform(0.01, 1)
+        a = H.disc_rect_area(cx, cy, r, x0, x0 + w, y0, y0 + h)
+        b = hohlraum_qoi.disc_cell_area(cx, cy, r, x0, x0 + w, y0, y0 + h)
+        assert abs(a - b) <= 1e-12 * math.pi * r * r
+
+
+@pytest.mark.parametrize("n", [104, 260, 333])
+def test_probe_cells_match_the_oracle(n):
+    from oracle import hohlraum_qoi
+
+    p = I.hohlraum(n=n, M=32)
+    got = H.probe_cells(p)
+    want = hohlraum_qoi.probe_cells(p)
+    assert got["n_probes"] == want["n_probes"] == 4 and got["n_windows"] == want["n_windows"] == 10
+    c = got["cells"]
+    key_g = sorted(zip(c["probe"], c["cell"] // n, c["cell"] % n, c["weight"]))
+    key_o = sorted(zip(want["probe"], want["cell_j"], want["cell_i"], want["weight"]))
+    assert [k[:3] for k in key_g] == [tuple(int(v) for v in k[:3]) for k in key_o]
+    np.testing.assert_allclose([k[3] for k in key_g], [k[3] for k in key_o], rtol=1e-9, atol=1e-13)

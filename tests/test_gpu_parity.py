@@ -283,3 +283,17 @@ def test_lattice700_full_run_matches_golden(sv):
     ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"])
     print(rep)
     assert ok, rep
+
+
+@pytest.mark.parametrize("N,order", [(5, 2), (22, 2), (22, 1)])
+def test_tessellation_quadrature_random_state(sv, orc, N, order):
+    """The paper's tessellation quadrature (M = 4 N^2: 100, and 1936 at the
+    finest N = 22, where ordinate groups run to ~242 ordinates): every element
+    of psi and phi and every QoI after two Heun steps from a random state on a
+    ragged lattice grid with reflective and inflow sides."""
+    p = I.lattice(71, order=order, stepper=I.HEUN, quad=I.tessellation_quadrature(N),
+                  bc=(I.BC_REFLECT, I.BC_INFLOW, I.BC_REFLECT, I.BC_VACUUM))
+    p = p.replace(inflow=(0.0, 0.6, 0.0, 0.0))
+    psi0 = I.random_state(p, 31 + N)
+    g, o = _run_both(sv, orc, p, 2, psi0=psi0)
+    _check(p, g, o, 2)

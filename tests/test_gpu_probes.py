@@ -1,0 +1,139 @@
+"""Space-time probes (Hohlraum QoI-1, Sec. 3.2.1) on the GPU, through the C
+ABI, against the FP64 oracle.
+
+Each probe block of the finalize reduces phi, J_x and J_y of the stage input
+over the probe's weighted cells into the window of the current step, with the
+stage's time weight. Against the oracle the window averages agree to 1e-5 of
+the probe's phi scale (J_x and J_y are bounded by phi); across batch
+membership (Euler's alternating buffers included) and graph replay they are
+bit-identical.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17284_amd import solver
+
+    return solver
+
+
+def _compare(g, o, rtol=1e-5):
+    assert g.shape == o.shape
+    scale = np.abs(o[:, :, 0]).max(axis=0)  # per probe: its largest window phi
+    err = np.abs(g - o)
+    bound = rtol * np.abs(o) + rtol * scale[None, :, None]
+    print("max err / bound:", float((err / bound).max()))
+    assert np.all(err <= bound), (g, o)
+
+
+def _run(sv, orc, p, geom=None, steps=None, psi0=None, rtol=1e-5, **kw):
+    """Probes of the GPU path (product geometry) vs the oracle (its own
+    geometry, pinned separately; the two agree to 1e-9 on the CPU)."""
+    from oracle import hohlraum_qoi
+
+    from paper_2505_17284_amd import hohlraum
+
+    geom = geom or {}
+    print(f"[case] probes {p.name} n=({p.nx},{p.ny}) M={p.M} order={p.order} stepper={p.stepper} "
+          f"dtype={p.psi_dtype} steps={steps} geom={geom} kw={kw}", flush=True)
+    plan = sv.Plan(p, psi0=psi0, probes=hohlraum.probe_cells(p, **geom), **kw)
+    try:
+        plan.run(steps)
+        g = plan.probes()
+    finally:
+        plan.close()
+    o = orc.solve(p, steps=steps, psi0=psi0, probes=hohlraum_qoi.probe_cells(p, **geom))["probes"]
+    _compare(g, o, rtol)
+    return g
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("stepper", [I.EULER, I.HEUN])
+def test_probes_random_materials(sv, orc, order, stepper):
+    """Ragged grid, random materials and state, two probes of radius 0.06
+    (about 14 cells each), 5 windows over 11 steps (uneven windows)."""
+    p = I.random_materials(70, 37, 5, seed=21, M=32, order=order, stepper=stepper,
+                           bc=(I.BC_INFLOW, I.BC_REFLECT, I.BC_VACUUM, I.BC_INFLOW), inflow=(0.8, 0, 0, 0.4),
+                           t_end=0.275)
+    geom = dict(centres=((1.2, 0.9), (2.71, 0.33)), r=0.06, n_windows=5)
+    _run(sv, orc, p, geom, psi0=I.random_state(p, 22))
+
+
+def test_hohlraum_probes_uneven_windows(sv, orc):
+    """The paper's four probes on the Hohlraum layout at n = 104 (balls
+    between cells), 16 steps into 10 windows."""
+    _run(sv, orc, I.hohlraum(104, 32, t_end=0.1))
+
+
+def test_probes_bf16_storage(sv, orc):
+    _run(sv, orc, I.hohlraum(104, 32, t_end=0.1, psi_dtype="bf16"), rtol=1e-2)
+
+
+def test_probes_batch_and_graph_bit_identical(sv):
+    """A batch member's probes (Euler: the finalize reads A and B in turn)
+    and a graph-replayed plan's equal the plan's own eager run."""
+    from paper_2505_17284_amd import batch, hohlraum
+
+    for order, stepper in ((1, I.EULER), (2, I.HEUN)):
+        p = I.hohlraum(104, 32, order=order, stepper=stepper, t_end=0.2)
+        pr = hohlraum.probe_cells(p)
+        print(f"[case] probes alone/batch/graph stepper={stepper}", flush=True)
+        plan = sv.Plan(p, probes=pr, rows_per_wave=2, waves_per_group=4)
+        plan.run()
+        alone = plan.probes()
+        plan.close()
+        plan = sv.Plan(p, probes=pr, rows_per_wave=2, waves_per_group=4, graph_steps=4)
+        plan.run()
+        graphed = plan.probes()
+        plan.close()
+        assert np.array_equal(graphed, alone)
+        assert np.all(np.isfinite(alone))
+        b = batch.Batch(order=order, stepper=stepper, max_instances=4, steps_per_run=5)
+        try:
+            s0 = b.admit(I.lattice(70, 32, order=order, stepper=stepper, t_end=0.3))
+            s1 = b.admit(p, probes=pr)
+            while b.unfinished():
+                b.run()
+            assert np.array_equal(b.plan(s1).probes(), alone)
+            assert b.status(s0)[0]
+        finally:
+            b.close()
+
+
+def test_hohlraum260_full_run_probes_match_golden(sv):
+    """Full Hohlraum solve (260^2, 256 ordinates, minmod, Heun, 1040 steps):
+    QoI-1 (4 probes x 10 windows x phi, J_x, J_y) against the oracle's values
+    stored by tests/golden/make_oracle_goldens.py, to 1e-4 of each probe's
+    phi scale."""
+    from paper_2505_17284_amd import hohlraum
+
+    path = os.path.join(GOLDEN, "oracle_hohlraum260_M256_heun2.json")
+    with open(path) as f:
+        gold = json.load(f)
+    if "probes" not in gold:
+        pytest.skip("golden has no probe values")
+    p = I.hohlraum(260, 256)
+    print("[case] probes hohlraum260 full run", flush=True)
+    plan = sv.Plan(p, probes=hohlraum.probe_cells(p))
+    try:
+        plan.run()
+        g = plan.probes()
+    finally:
+        plan.close()
+    _compare(g, np.array(gold["probes"]), rtol=1e-4)

@@ -118,3 +118,22 @@ def test_oracle_reference_run_plausible_against_the_paper():
     assert band["V_G"] == pytest.approx(tab["QoI-4"]["mean"], rel=0.15)
     assert 0.25 * band["A_G"] < band["A_L"] < band["A_G"]
     assert band["length"] == pytest.approx(2.2, rel=1e-12)
+
+
+def test_oracle_probe_windows_show_the_papers_symmetry():
+    """QoI-1 of the stored run: the paper observes that the two probes left
+    and right of the capsule share phi and J_y and have opposite J_x, the two
+    above and below share phi and J_x and have opposite J_y, and each pair's
+    cross current vanishes (R23 bounds the mirror defect at second order)."""
+    with open(os.path.join(GOLDEN, "oracle_hohlraum260_M256_heun2.json")) as f:
+        g = json.load(f)
+    if "probes" not in g:
+        pytest.skip("golden has no probe values")
+    a = np.array(g["probes"])  # [window][probe][phi, J_x, J_y]
+    tol = 1e-5 * np.abs(a[:, :, 0]).max()
+    for lo, hi, axis in ((0, 1, 1), (2, 3, 2)):
+        other = 3 - axis
+        assert np.abs(a[:, lo, 0] - a[:, hi, 0]).max() <= tol
+        assert np.abs(a[:, lo, axis] + a[:, hi, axis]).max() <= tol
+        assert np.abs(a[:, lo, other]).max() <= tol and np.abs(a[:, hi, other]).max() <= tol
+    assert a[-1, 0, 0] > 0.5 and a[-1, 0, 1] > 0  # particles reach the probe and stream inwards
