@@ -212,13 +212,22 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
     int g = 1;
     while ((tiles * g < 4096 || g < 8) && (P->M + 2 * g - 1) / (2 * g) >= 8) g *= 2;
     *group_size = (P->M + g - 1) / g;
+    // With FP32 storage, groups of more than 32 ordinates measured slower on
+    // large M: 700 x 700 with 1936 ordinates, stage 1 1.83 ms with 32 per
+    // group vs 2.27 ms with 242; the 1300 x 1300 x 512 cavity is level (1.61
+    // vs 1.65 ms with 64). With BF16 storage large groups are faster (1.74 vs
+    // 1.85 ms with 242 vs 32 on the 1936-ordinate lattice), so no cap there.
+    if (P->dtype == SN_F32) *group_size = std::min(*group_size, 32);
     // Heun's averaging stage also streams psi^n; with FP32 storage its LDS
     // slots are twice those of the update stage, and twice the groups (half
-    // the ordinates each, while that leaves at least 16) measured faster: 356
-    // vs 372 us per launch on the 700 x 700 x 256 lattice, 2.38 vs 2.62 ms on
-    // the 1300 x 1300 x 512 cavity. With BF16 storage the halving measured
-    // slower (368 vs 330 us on the lattice).
-    *group_size_avg = (*group_size >= 32 && P->dtype == SN_F32) ? (*group_size + 1) / 2 : *group_size;
+    // the ordinates each, while that leaves at least 16) measured faster on
+    // the 700 x 700 grids: 356 vs 372 us per launch with 256 ordinates, 2.61
+    // vs 2.69 ms with 1936. On grids of more than 2^20 cells the finalize's
+    // extra phi partials (one plane per group) cost more than that gains
+    // (the 1300 x 1300 x 512 cavity: 4.16 vs 4.22 ms per step). With BF16
+    // storage the halving measured slower (368 vs 330 us on the lattice).
+    const bool halve = *group_size >= 32 && P->dtype == SN_F32 && (int64_t)P->nx * P->ny <= (1 << 20);
+    *group_size_avg = halve ? (*group_size + 1) / 2 : *group_size;
 }
 
 sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int waves) {
