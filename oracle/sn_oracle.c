@@ -15,6 +15,8 @@
  *     reconstruction of the upwind cell): Sec. 4.2, eqs. eq_sn_2d_eqn_fv and
  *     eq_upwind1stOrder, on square cells (edge length h, area h^2; the flux sum
  *     is divided by the cell area).
+ *   - order 3: the Green-Gauss gradient with the Venkatakrishnan limiter
+ *     (Sec. 4.2, eq. eq_V_limiter) on square cells.
  *   - ghost cells carrying the inflow value, first-order fluxes on boundary
  *     faces: end of Sec. 4.2.
  *   - forward Euler and Heun's method (SSP-RK2) with dt = T / N_t: Sec. 4.3,
@@ -147,12 +149,66 @@ static double cell_y(const orc_problem *P, const double *psi, int k, int j, int 
     return PSI(P, psi, k, j, i);
 }
 
+/* Venkatakrishnan-limited reconstruction (Sec. 4.2, eq. eq_V_limiter) of
+ * ordinate k in cell (i, j) at the midpoint of one of its faces: dir 0 for an
+ * x-face, 1 for a y-face; sgn +1 for the face on the cell's + side.
+ *   gradient  g = (1/A) sum_faces l n (psi_i + psi_j)/2; on a square cell of
+ *             side h the cell's own value cancels: g = ((E - W), (N - S)) / (2h)
+ *   face      R = psi_i + L g . r, r from the cell centre to the face midpoint
+ *             (|r| = h/2), so g . r = +-(E - W)/4 or +-(N - S)/4
+ *   limiter   L = min over the four faces of
+ *             ((b^2 + e^2) + 2 D b) / (b^2 + 2 D^2 + b D + e^2), and 1 where D = 0,
+ *             with D = g . r of that face (reading: the increment g . r; the
+ *             printed factor 1/2 would let face values leave the
+ *             neighbourhood's range), b = max - psi_i for D > 0 and
+ *             min - psi_i for D < 0 over the cell and its four neighbours,
+ *             e = K A^3 with K = 1, A = h^2.
+ * Neighbours outside the grid are ghost cells holding the side's ghost value
+ * for every ordinate. */
+static double venkat(const orc_problem *P, const double *psi, int k, int j, int i, int dir, int sgn)
+{
+    double c = PSI(P, psi, k, j, i);
+    double W = cell_x(P, psi, k, j, i - 1), E = cell_x(P, psi, k, j, i + 1);
+    double S = cell_y(P, psi, k, j - 1, i), N = cell_y(P, psi, k, j + 1, i);
+    double ax = 0.25 * (E - W), ay = 0.25 * (N - S);
+    double mx = c, mn = c, bM, bm, e, e2, L = HUGE_VAL, D[4];
+    int f;
+    if (W > mx) mx = W;
+    if (E > mx) mx = E;
+    if (S > mx) mx = S;
+    if (N > mx) mx = N;
+    if (W < mn) mn = W;
+    if (E < mn) mn = E;
+    if (S < mn) mn = S;
+    if (N < mn) mn = N;
+    bM = mx - c;
+    bm = mn - c;
+    e = P->h * P->h * P->h * P->h * P->h * P->h;
+    e2 = e * e;
+    D[0] = ax;
+    D[1] = -ax;
+    D[2] = ay;
+    D[3] = -ay;
+    for (f = 0; f < 4; ++f) {
+        double d = D[f], b, v;
+        if (d == 0.0) {
+            v = 1.0;
+        } else {
+            b = d > 0.0 ? bM : bm;
+            v = (b * b + e2 + 2.0 * d * b) / (b * b + 2.0 * d * d + b * d + e2);
+        }
+        if (v < L) L = v; /* may exceed 1: the factor peaks near 1.094 */
+    }
+    return c + sgn * L * (dir == 0 ? ax : ay);
+}
+
 /* Upwind numerical trace on the x-face f (between cells f-1 and f) of row j,
  * f = 0..nx (eq. eq_upwind1stOrder). Boundary faces take the ghost for
  * incoming ordinates and the boundary cell value for outgoing ones (first
  * order). Interior faces take the reconstruction of the upwind cell u at the
  * face: psi_u for order 1; psi_u +- 1/2 minmod(psi_u - psi_{u-1},
  * psi_{u+1} - psi_u) for order 2, "+" when the face is the cell's right face;
+ * the Venkatakrishnan-limited reconstruction (venkat) for order 3;
  * a neighbour outside the grid is the ghost value. */
 double orc_face_x(const orc_problem *P, const double *psi, int k, int f, int j)
 {
@@ -164,6 +220,7 @@ double orc_face_x(const orc_problem *P, const double *psi, int k, int f, int j)
         double pu = PSI(P, psi, k, j, u);
         double slope;
         if (P->order == 1) return pu;
+        if (P->order == 3) return venkat(P, psi, k, j, u, 0, xi > 0.0 ? 1 : -1);
         slope = minmod(pu - cell_x(P, psi, k, j, u - 1), cell_x(P, psi, k, j, u + 1) - pu);
         return xi > 0.0 ? pu + 0.5 * slope : pu - 0.5 * slope;
     }
@@ -180,6 +237,7 @@ double orc_face_y(const orc_problem *P, const double *psi, int k, int i, int f)
         double pu = PSI(P, psi, k, u, i);
         double slope;
         if (P->order == 1) return pu;
+        if (P->order == 3) return venkat(P, psi, k, u, i, 1, eta > 0.0 ? 1 : -1);
         slope = minmod(pu - cell_y(P, psi, k, u - 1, i), cell_y(P, psi, k, u + 1, i) - pu);
         return eta > 0.0 ? pu + 0.5 * slope : pu - 0.5 * slope;
     }

@@ -2,10 +2,11 @@
 
 These are independent of the oracle's loops: the first-order operator is
 assembled face by face in conservative form (each face's flux leaves one cell
-and enters the other) as a dense matrix, and the second-order operator is
-evaluated face by face in Python on a ghost-padded array. Both follow the
-cell balance with the upwind trace of arXiv 2505.17284 Sec. 4.2 (eqs.
-eq_sn_2d_eqn_fv, eq_upwind1stOrder) on square cells.
+and enters the other) as a dense matrix, and the second-order operators
+(minmod; the Venkatakrishnan-limited gradient, as vectors) are evaluated face
+by face in Python on a ghost-padded array. All follow the cell balance with
+the upwind trace of arXiv 2505.17284 Sec. 4.2 (eqs. eq_sn_2d_eqn_fv,
+eq_upwind1stOrder, eq_V_limiter) on square cells.
 """
 
 import numpy as np
@@ -149,6 +150,65 @@ def rhs_second_order(p, psi):
                 else:
                     c = f + 1
                     fy[f, i] = col[c] - 0.5 * _minmod(col[c] - col[c - 1], col[c + 1] - col[c])
+        div = xi * (fx[:, 1:] - fx[:, :-1]) / h + eta * (fy[1:, :] - fy[:-1, :]) / h
+        F[k] = -div - (sa + ss) * psi[k] + ss / (2 * np.pi) * phi + q
+    return F
+
+
+def rhs_venkat(p, psi):
+    """F(psi) for order 3 (Venkatakrishnan-limited Green-Gauss reconstruction,
+    Sec. 4.2), face by face on ghost-padded ordinates: every interior face
+    takes the upwind cell's limited linear reconstruction at the face
+    midpoint, boundary faces are first order."""
+    M, nx, ny, h = p.M, p.nx, p.ny, p.h
+    psi = np.asarray(psi).reshape(M, ny, nx)
+    phi = np.einsum("k,kji->ji", p.quad.w, psi)
+    F = np.zeros_like(psi)
+    sa = p.sigma_a[p.region]
+    ss = p.sigma_s[p.region]
+    q = p.q[p.region]
+    eps2 = (h ** 2) ** 6  # (K A^3)^2 with K = 1, A = h^2
+
+    def limited(g, jp, ip, normal):
+        """Face value of padded cell (jp, ip) at its face with outward unit normal."""
+        c = g[jp, ip]
+        nb = [g[jp, ip - 1], g[jp, ip + 1], g[jp - 1, ip], g[jp + 1, ip]]  # W E S N
+        grad = np.array([(nb[1] - nb[0]) / (2 * h), (nb[3] - nb[2]) / (2 * h)])
+        lo, hi = min([c] + nb), max([c] + nb)
+        factors = []
+        for n in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            d = grad @ (np.array(n) * h / 2)  # increment to that face's midpoint
+            if d > 0:
+                b = hi - c
+            elif d < 0:
+                b = lo - c
+            else:
+                factors.append(1.0)
+                continue
+            factors.append(((b * b + eps2) * d + 2 * d * d * b) / d / (b * b + 2 * d * d + b * d + eps2))
+        return c + min(factors) * (grad @ (np.array(normal) * h / 2))
+
+    for k in range(M):
+        g = _padded(p, psi, k)
+        xi, eta = p.quad.xi[k], p.quad.eta[k]
+        fx = np.zeros((ny, nx + 1))
+        fy = np.zeros((ny + 1, nx))
+        for j in range(ny):
+            for f in range(nx + 1):
+                if f == 0 or f == nx:
+                    fx[j, f] = g[j + 1, f] if xi > 0 else g[j + 1, f + 1]
+                elif xi > 0:
+                    fx[j, f] = limited(g, j + 1, f, (1, 0))  # cell f-1, its east face
+                else:
+                    fx[j, f] = limited(g, j + 1, f + 1, (-1, 0))  # cell f, its west face
+        for i in range(nx):
+            for f in range(ny + 1):
+                if f == 0 or f == ny:
+                    fy[f, i] = g[f, i + 1] if eta > 0 else g[f + 1, i + 1]
+                elif eta > 0:
+                    fy[f, i] = limited(g, f, i + 1, (0, 1))
+                else:
+                    fy[f, i] = limited(g, f + 1, i + 1, (0, -1))
         div = xi * (fx[:, 1:] - fx[:, :-1]) / h + eta * (fy[1:, :] - fy[:-1, :]) / h
         F[k] = -div - (sa + ss) * psi[k] + ss / (2 * np.pi) * phi + q
     return F
