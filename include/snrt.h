@@ -88,8 +88,10 @@ typedef struct sn_probe_cell {
  *                 (>= 0, finite) and isotropic source per ordinate (finite).
  *  tally          [n_regions] absorption tally id (< n_tallies <= 8).
  *  bc, inflow     boundary kind and inflow value per side (W, E, S, N).
- *  order          1 (first-order upwind) or 2 (minmod MUSCL, boundary faces
- *                 first order).
+ *  order          1 (first-order upwind), 2 (minmod MUSCL) or 3 (Green-Gauss
+ *                 gradient with the Venkatakrishnan limiter, eq. eq_V_limiter;
+ *                 its ghost cells hold the side's ghost value for every
+ *                 ordinate); boundary faces are first order.
  *  stepper        SN_EULER or SN_HEUN.
  *  cfl, t_end     dt = t_end / N_t with N_t = ceil(t_end / (cfl h) - 1e-9).
  *  rects          [n_rects][4] = (i0, j0, i1, j1), half-open cell ranges

@@ -41,16 +41,19 @@ __device__ __forceinline__ void ghost_update(const GhostArgs& a, int k, int idx)
     const T* pmy = psi + (int64_t)o.my * a.plane;
     const int64_t P = a.pitch;
     const int nx = a.nx, ny = a.ny, ox = a.ox;
+    // with all_dirs (order 3) the side's ghost value also goes to the
+    // ordinates leaving through it
+    const bool all = a.all_dirs != 0;
     if (idx < ny) {
         const int64_t row = (int64_t)(idx + kGhost) * P;
-        if (sx) {  // enters through W
+        if (sx || all) {  // enters through W
             const float g = a.bc[kW] == kReflect ? ld(pmx + row + ox) : a.ghost[kW];
             st(pk + row + ox - 1, g);
             st(pk + row + ox - 2, g);
         } else {
             st(pk + row + ox - 1, ld(pk + row + ox));
         }
-        if (!sx) {  // enters through E
+        if (!sx || all) {  // enters through E
             const float g = a.bc[kE] == kReflect ? ld(pmx + row + ox + nx - 1) : a.ghost[kE];
             st(pk + row + ox + nx, g);
             st(pk + row + ox + nx + 1, g);
@@ -60,14 +63,14 @@ __device__ __forceinline__ void ghost_update(const GhostArgs& a, int k, int idx)
     }
     if (idx < nx) {
         const int64_t col = idx + ox;
-        if (sy) {  // enters through S
+        if (sy || all) {  // enters through S
             const float g = a.bc[kS] == kReflect ? ld(pmy + kGhost * P + col) : a.ghost[kS];
             st(pk + 1 * P + col, g);
             st(pk + 0 * P + col, g);
         } else {
             st(pk + 1 * P + col, ld(pk + kGhost * P + col));
         }
-        if (!sy) {  // enters through N
+        if (!sy || all) {  // enters through N
             const float g = a.bc[kN] == kReflect ? ld(pmy + (int64_t)(ny - 1 + kGhost) * P + col) : a.ghost[kN];
             st(pk + (int64_t)(ny + kGhost) * P + col, g);
             st(pk + (int64_t)(ny + kGhost + 1) * P + col, g);
@@ -328,6 +331,8 @@ hipError_t launch_stage(int order, int mode, int dtype, int rows, int waves, con
         return dtype == 0 ? launch_stage_o1_f32(mode, rows, waves, a, s) : launch_stage_o1_bf16(mode, rows, waves, a, s);
     if (order == 2)
         return dtype == 0 ? launch_stage_o2_f32(mode, rows, waves, a, s) : launch_stage_o2_bf16(mode, rows, waves, a, s);
+    if (order == 3)
+        return dtype == 0 ? launch_stage_o3_f32(mode, rows, waves, a, s) : launch_stage_o3_bf16(mode, rows, waves, a, s);
     return hipErrorInvalidValue;
 }
 
@@ -339,6 +344,9 @@ hipError_t launch_stage_batch(int order, int mode, int dtype, int rows, int wave
     if (order == 2)
         return dtype == 0 ? launch_batch_o2_f32(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s)
                           : launch_batch_o2_bf16(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
+    if (order == 3)
+        return dtype == 0 ? launch_batch_o3_f32(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s)
+                          : launch_batch_o3_bf16(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
     return hipErrorInvalidValue;
 }
 

@@ -84,6 +84,7 @@ struct StageArgs {
     int32_t n_tallies, n_rects, nq;
     int32_t bc[4];
     int32_t rect[kMaxRects][4];
+    float eps2;             // order 3: the limiter's epsilon^2, (h^2)^6
 };
 
 // One batched launch over several instances (plans): the grid strides over
@@ -114,6 +115,7 @@ struct GhostArgs {
     int32_t nx, ny, pitch, M, ox;
     int32_t bc[4];
     float ghost[4];  // inflow value per side (0 for vacuum)
+    int32_t all_dirs;  // 1 (order 3): every ordinate's ghost cells hold the side's ghost value
 };
 
 struct FinalizeArgs {
@@ -198,6 +200,8 @@ hipError_t launch_stage_o1_f32(int mode, int rows, int waves, const StageArgs& a
 hipError_t launch_stage_o2_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o1_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o2_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_o3_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_o3_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_batch_o1_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
                                int max_rects, hipStream_t s);
 hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
@@ -205,6 +209,10 @@ hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch&
 hipError_t launch_batch_o1_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
                                int max_rects, hipStream_t s);
 hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s);
+hipError_t launch_batch_o3_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s);
+hipError_t launch_batch_o3_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
                                int max_rects, hipStream_t s);
 
 }  // namespace snk

@@ -170,6 +170,33 @@ __device__ __forceinline__ float minmod(float a, float b) {
     return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
 }
 
+// Order 3 (Sec. 4.2, eq. eq_V_limiter): the Venkatakrishnan factor of one
+// face, whose reconstruction increment is d, with b_max = max - c and b_min
+// = min - c over the cell and its four neighbours; 1 where d = 0.
+__device__ __forceinline__ float venkat_face(float d, float bmax, float bmin, float e2) {
+    const float b = d > 0.0f ? bmax : bmin;
+    const float num = fmaf(2.0f * d, b, fmaf(b, b, e2));
+    const float den = fmaf(b, d, fmaf(2.0f * d, d, fmaf(b, b, e2)));
+    return d == 0.0f ? 1.0f : num / den;
+}
+
+// The limited reconstruction of a cell with value c and neighbours W, E, S,
+// N: returns the limiter L (the minimum of the four faces' factors) and the
+// increments to its east and north face midpoints, ax = g_x h/2 = (E - W)/4
+// and ay = (N - S)/4 (the Green-Gauss gradient of a square cell is the
+// central difference). Face values: c + L ax (east), c - L ax (west), c + L
+// ay (north), c - L ay (south).
+__device__ __forceinline__ float venkat_limit(float c, float W, float E, float S, float N, float e2, float& ax,
+                                              float& ay) {
+    ax = 0.25f * (E - W);
+    ay = 0.25f * (N - S);
+    const float mx = fmaxf(fmaxf(fmaxf(W, E), fmaxf(S, N)), c);
+    const float mn = fminf(fminf(fminf(W, E), fminf(S, N)), c);
+    const float bmax = mx - c, bmin = mn - c;
+    return fminf(fminf(venkat_face(ax, bmax, bmin, e2), venkat_face(-ax, bmax, bmin, e2)),
+                 fminf(venkat_face(ay, bmax, bmin, e2), venkat_face(-ay, bmax, bmin, e2)));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
@@ -225,6 +252,7 @@ struct WaveCtx {
     // holding column 0) and nx, nx+1 (lane holding column nx-1).
     uint32_t gw1, gw2, ge1, ge2;
     bool ge_first;       // column nx-1 is the lane's first cell
+    bool xb_w, xb_e0, xb_e1;  // the lane's cell 0 west face / cell 0 east face / cell 1 east face is on the grid's boundary
     bool ghost_wave;     // the wave holds a boundary cell (wave-uniform)
     uint32_t pitchb;     // bytes per padded row
     uint32_t seed;       // BF16 storage: stages finalised so far (rounding bits), else 0
@@ -258,7 +286,9 @@ struct WaveCtx {
 #define SN_RING_SLOTS_NO_OLD 5
 #endif
 
-template <typename T, int TY, int W, int MODE>
+// XH: extra x-halo rows, one above and one below the output rows (order 3,
+// whose limiter needs the cells beside the tile in the rows next to a face).
+template <typename T, int TY, int W, int MODE, int XH = 0>
 struct Ring {
     static constexpr int kSlots = MODE == kAverage ? SN_RING_SLOTS : SN_RING_SLOTS_NO_OLD;  // in flight + computed
     static_assert(kSlots >= 2 && kSlots <= 5, "ring depth");
@@ -272,12 +302,14 @@ struct Ring {
     static constexpr int kDmaOld = (kOldRows + kRowsPerDma - 1) / kRowsPerDma;
     static constexpr int kOldRow0 = kDmaStencil * kRowsPerDma;           // first psi^n row of a slot
     static constexpr int kSlotRows = kOldRow0 + kDmaOld * kRowsPerDma;
-    // x-halo of the output rows: cells -2, -1, 128, 129 of the tile, one
-    // dword per lane (4 lanes per row for FP32, 2 for BF16)
+    // x-halo of the output rows (and XH / 2 more rows on each side): cells
+    // -2, -1, 128, 129 of the tile, one dword per lane (4 lanes per row for
+    // FP32, 2 for BF16)
+    static constexpr int kHaloRows = W * TY + XH;
     static constexpr int kHaloRowBytes = 4 * (int)sizeof(T);
     static constexpr int kHaloLanesPerRow = kHaloRowBytes / 4;
     static constexpr int kHaloRowsPerDma = kWave / kHaloLanesPerRow;
-    static constexpr int kDmaHalo = (W * TY + kHaloRowsPerDma - 1) / kHaloRowsPerDma;
+    static constexpr int kDmaHalo = (kHaloRows + kHaloRowsPerDma - 1) / kHaloRowsPerDma;
     static constexpr int kHaloOffset = kSlotRows * kRowBytes;             // bytes into the slot
     static constexpr int kSlotBytes = kHaloOffset + kDmaHalo * kWave * 4;
     static constexpr int kDmaPerOrd = kDmaStencil + kDmaOld + kDmaHalo;  // copies per ordinate
@@ -287,6 +319,10 @@ struct Ring {
     // 63: waiting for more is only conservative)
     static constexpr int wait_ahead(int ahead) { return kDmaPerOrd * ahead < 64 ? kDmaPerOrd * ahead : 63; }
 };
+
+// Extra x-halo rows of an order.
+template <int ORDER>
+constexpr int kExtraHalo = ORDER == 3 ? 2 : 0;
 
 using lds_ptr = __attribute__((address_space(3))) void*;
 
@@ -314,9 +350,9 @@ struct LoaderOffsets {
 // the compute lanes read. The x-halo dwords: lane l covers dword
 // (l % kHaloLanesPerRow) of output row l / kHaloLanesPerRow, the first half
 // of a row's dwords left of the tile, the rest right of it.
-template <typename T, int TY, int W, int MODE>
+template <typename T, int TY, int W, int MODE, int XH>
 __device__ __forceinline__ LoaderOffsets loader_offsets(SArgs a, int col0, uint32_t tile_off, uint32_t pitchb) {
-    using R = Ring<T, TY, W, MODE>;
+    using R = Ring<T, TY, W, MODE, XH>;
     constexpr int kCellsPerCopy = R::kDmaBytes / (int)sizeof(T);
     const int lane = threadIdx.x & (kWave - 1);
     LoaderOffsets o;
@@ -330,7 +366,7 @@ __device__ __forceinline__ LoaderOffsets loader_offsets(SArgs a, int col0, uint3
     // rows past the workgroup's output rows, and east cells past the grid's
     // ghost cells, are not needed
     const bool right_needed = col0 + kTileX < a.nx + kGhost;
-    o.halo = hr >= W * TY || (e >= half && !right_needed)
+    o.halo = hr >= R::kHaloRows || (e >= half && !right_needed)
                  ? kDropOffset
                  : (e < half ? tile_off - 2 * (uint32_t)sizeof(T) + 4 * e
                              : tile_off + (uint32_t)(kTileX * sizeof(T)) + 4 * (e - half)) +
@@ -339,10 +375,10 @@ __device__ __forceinline__ LoaderOffsets loader_offsets(SArgs a, int col0, uint3
 }
 
 // Loader: ordinate k's rows into ring slot `slot`.
-template <typename T, int TY, int W, int MODE>
+template <typename T, int TY, int W, int MODE, int XH>
 __device__ __forceinline__ void ring_issue(SArgs a, int k, int yw, const LoaderOffsets& lo, uint32_t pitchb,
                                            uint32_t planeb, char* slot) {
-    using R = Ring<T, TY, W, MODE>;
+    using R = Ring<T, TY, W, MODE, XH>;
     const rsrc_t r = make_rsrc(static_cast<const char*>(a.psi_in) + (size_t)k * planeb, planeb);
 #pragma unroll
     for (int i = 0; i < R::kDmaStencil; ++i)
@@ -352,7 +388,8 @@ __device__ __forceinline__ void ring_issue(SArgs a, int k, int yw, const LoaderO
 #pragma unroll
     for (int i = 0; i < R::kDmaHalo; ++i)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(slot + R::kHaloOffset + i * kWave * 4), 4, lo.halo,
-                                                 (uint32_t)(yw + kGhost + i * R::kHaloRowsPerDma) * pitchb, 0, 0);
+                                                 (uint32_t)(yw + kGhost - XH / 2 + i * R::kHaloRowsPerDma) * pitchb,
+                                                 0, 0);
     if (MODE == kAverage) {
         const rsrc_t ro = make_rsrc(static_cast<const char*>(a.psi_old) + (size_t)k * planeb, planeb);
 #pragma unroll
@@ -441,11 +478,47 @@ __device__ __forceinline__ void write_frame(SArgs a, const OrdConst& o, int k, i
     }
 }
 
+// Order 3: every ordinate's ghost cells hold the side's ghost value (set at
+// init on vacuum and inflow sides, never rewritten). On a reflective side the
+// ghost of ordinate k is its mirror's boundary cell, so every ordinate writes
+// its boundary cells into its mirror's ghost layers, entering or leaving.
+template <typename T, int TY>
+__device__ __forceinline__ void write_frame_all(SArgs a, const OrdConst& o, int j, uint32_t rowb,
+                                                const WaveCtx<TY>& w, float2 v) {
+    const char* out = static_cast<const char*>(a.psi_out);
+    if (a.bc[kW] == kReflect || a.bc[kE] == kReflect) {
+        const rsrc_t rm = make_rsrc(out + (size_t)o.mx * w.planeb, w.planeb);
+        if (a.bc[kW] == kReflect) {
+            Store<T>::bstore1(rm, w.gw1, rowb, v.x);
+            Store<T>::bstore1(rm, w.gw2, rowb, v.x);
+        }
+        if (a.bc[kE] == kReflect) {
+            const float ve = w.ge_first ? v.x : v.y;
+            Store<T>::bstore1(rm, w.ge1, rowb, ve);
+            Store<T>::bstore1(rm, w.ge2, rowb, ve);
+        }
+    }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const bool s_side = side == 0;
+        if (a.bc[s_side ? kS : kN] != kReflect || j != (s_side ? 0 : a.ny - 1)) continue;
+        const uint32_t g1 = (uint32_t)(s_side ? 1 : a.ny + kGhost) * w.pitchb;
+        const uint32_t g2 = (uint32_t)(s_side ? 0 : a.ny + kGhost + 1) * w.pitchb;
+        const rsrc_t rm = make_rsrc(out + (size_t)o.my * w.planeb, w.planeb);
+        Store<T>::bstore2(rm, w.store_off, g1, v);
+        Store<T>::bstore2(rm, w.store_off, g2, v);
+        if (w.ragged) {
+            Store<T>::bstore1(rm, w.single_off, g1, v.x);
+            Store<T>::bstore1(rm, w.single_off, g2, v.x);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- one ordinate
 // Window row r holds grid row y0 - 2 + r; output row t is window row t + 2.
 template <int ORDER, int MODE, typename T, int TY, int W, bool SX, bool SY>
 __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k, WaveCtx<TY>& w,
-                                               const float2 (&win)[TY + 4], const float4 (&halo)[TY],
+                                               const float2 (&win)[TY + 4], const float4 (&halo)[TY + kExtraHalo<ORDER>],
                                                const float2 (&oldv)[TY], double* facc) {
     constexpr int D = SY ? 0 : 1;  // y-traces of output row t: Ry[t + 1 + D] (south), Ry[t + 2 + D] (north)
     constexpr float HX = SX ? 0.5f : -0.5f;
@@ -453,7 +526,53 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
 
     // Reconstructions at the downwind y-face of window rows (eta > 0: top face).
     float2 Ry[TY + 3];
-    if (ORDER == 2) {
+    // Order 3: traces of the output rows' x-faces (west of cell 0, east of
+    // cells 0 and 1), first order on the grid's boundary faces.
+    float xw[TY], xe0[TY], xe1[TY];
+    if (ORDER == 3) {
+        // halo[h] is the x-halo of window row h + 1
+#pragma unroll
+        for (int r = 1; r <= TY + 2; ++r) {
+            const float c0 = win[r].x, c1 = win[r].y;
+            const float4 hv = halo[r - 1];               // cells -2, -1, 128, 129 of window row r
+            const float lf = lane_from_left(c1, hv.y);   // cell left of c0
+            const float rt = lane_from_right(c0, hv.z);  // cell right of c1
+            float ax0, ay0, ax1, ay1;
+            const float L0 = venkat_limit(c0, lf, c1, win[r - 1].x, win[r + 1].x, a.eps2, ax0, ay0);
+            const float L1 = venkat_limit(c1, c0, rt, win[r - 1].y, win[r + 1].y, a.eps2, ax1, ay1);
+            if (r >= 1 + D && r <= TY + 1 + D) {
+                // downwind y-face of row r; on the grid's boundary faces (south
+                // of row 0, north of row ny-1) the upwind cell's own value
+                const int gy = w.y0 - 2 + r;
+                const bool bnd = SY ? (gy == -1 || gy == a.ny - 1) : (gy == 0 || gy == a.ny);
+                const float sy = SY ? 1.0f : -1.0f;
+                Ry[r] = bnd ? win[r] : make_float2(fmaf(sy * L0, ay0, c0), fmaf(sy * L1, ay1, c1));
+            }
+            if (r >= 2 && r <= TY + 1) {
+                const int t = r - 2;
+                const float4 hu = halo[r - 2], hd = halo[r];  // rows r - 1 and r + 1
+                if (SX) {
+                    // east face of cell -1 (lane 0's left neighbour; its east
+                    // neighbour is lane 0's cell 0)
+                    float axm, aym;
+                    const float Lm = venkat_limit(hv.y, hv.x, c0, hu.y, hd.y, a.eps2, axm, aym);
+                    const float REl = lane_from_left(fmaf(L1, ax1, c1), fmaf(Lm, axm, hv.y));
+                    xw[t] = w.xb_w ? lf : REl;
+                    xe0[t] = w.xb_e0 ? c0 : fmaf(L0, ax0, c0);
+                    xe1[t] = w.xb_e1 ? c1 : fmaf(L1, ax1, c1);
+                } else {
+                    // west face of cell 128 (lane 63's right neighbour; its
+                    // west neighbour is lane 63's cell 1)
+                    float axp, ayp;
+                    const float Lp = venkat_limit(hv.z, c1, hv.w, hu.z, hd.z, a.eps2, axp, ayp);
+                    const float RWr = lane_from_right(fmaf(-L0, ax0, c0), fmaf(-Lp, axp, hv.z));
+                    xw[t] = w.xb_w ? c0 : fmaf(-L0, ax0, c0);
+                    xe0[t] = w.xb_e0 ? c1 : fmaf(-L1, ax1, c1);
+                    xe1[t] = w.xb_e1 ? rt : RWr;
+                }
+            }
+        }
+    } else if (ORDER == 2) {
         float2 dy[TY + 3];  // dy[r] = win[r + 1] - win[r]
 #pragma unroll
         for (int r = D; r <= TY + 1 + D; ++r) dy[r] = make_float2(win[r + 1].x - win[r].x, win[r + 1].y - win[r].y);
@@ -475,11 +594,17 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
         const int j = w.y0 + t;
         if (j >= a.ny) break;  // wave-uniform
         const float c0 = win[t + 2].x, c1 = win[t + 2].y;
-        const float4 hv = halo[t];  // cells -2, -1 and 128, 129 of the tile
+        const float4 hv = halo[ORDER == 3 ? t + 1 : t];  // cells -2, -1 and 128, 129 of the tile
         const float L = lane_from_left(c1, hv.y);    // cell left of c0 (lane 0: cell -1)
         const float Rn = lane_from_right(c0, hv.z);  // cell right of c1 (lane 63: cell 128)
         float dRx0, dRx1, tW0, tE0, tE1;       // x-differences and traces (west of cell 1 = east of cell 0)
-        if (ORDER == 2) {
+        if (ORDER == 3) {
+            tW0 = xw[t];
+            tE0 = xe0[t];
+            tE1 = xe1[t];
+            dRx0 = tE0 - tW0;
+            dRx1 = tE1 - tE0;
+        } else if (ORDER == 2) {
             const float d01 = c1 - c0;
             const float m0 = minmod(c0 - L, d01), m1 = minmod(d01, Rn - c1);
             const float R0 = fmaf(HX, m0, c0), R1 = fmaf(HX, m1, c1);
@@ -541,7 +666,10 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
             v = Store<T>::round2(v, r0, r1);
             Store<T>::bstore2(rout, w.store_off, rowb, v);  // halo and partial lanes drop the pair
             if (w.ragged) Store<T>::bstore1(rout, w.single_off, rowb, v.x);
-            if (w.ghost_wave) write_frame<T, TY, SX, SY>(a, o, k, j, rowb, rout, w, v);
+            if (w.ghost_wave) {
+                if (ORDER == 3) write_frame_all<T, TY>(a, o, j, rowb, w, v);
+                else write_frame<T, TY, SX, SY>(a, o, k, j, rowb, rout, w, v);
+            }
             w.phacc[t].x = fmaf(o.w, v.x, w.phacc[t].x);
             w.phacc[t].y = fmaf(o.w, v.y, w.phacc[t].y);
         }
@@ -563,7 +691,7 @@ using const_ord_ptr = const __attribute__((address_space(4))) OrdConst*;
 
 template <int ORDER, int MODE, typename T, int TY, int W>
 __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
-                                                 const float2 (&win)[TY + 4], const float4 (&halo)[TY],
+                                                 const float2 (&win)[TY + 4], const float4 (&halo)[TY + kExtraHalo<ORDER>],
                                                  const float2 (&oldv)[TY], double* facc) {
     const const_ord_ptr q = (const_ord_ptr)a.ord + k;
     OrdConst o;
@@ -598,10 +726,10 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nwg) {
     return xcd < rem ? xcd * (per + 1) + q8 : rem * (per + 1) + (xcd - rem) * per + q8;
 }
 
-template <typename T, int TY, int W, int MODE>
+template <typename T, int TY, int W, int MODE, int XH>
 struct StageLds {
     double red[W][kMaxQ];
-    alignas(16) char ring[Ring<T, TY, W, MODE>::kBytes];
+    alignas(16) char ring[Ring<T, TY, W, MODE, XH>::kBytes];
 };
 
 // The work of logical workgroup `logical` of one stage launch: tile and
@@ -609,8 +737,9 @@ struct StageLds {
 // 2 n_rects FP64 accumulators per thread.
 template <int ORDER, int MODE, typename T, int TY, int W>
 __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_all,
-                                           StageLds<T, TY, W, MODE>& lds) {
-    using R = Ring<T, TY, W, MODE>;
+                                           StageLds<T, TY, W, MODE, kExtraHalo<ORDER>>& lds) {
+    constexpr int XH = kExtraHalo<ORDER>;
+    using R = Ring<T, TY, W, MODE, XH>;
     auto& red = lds.red;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -629,12 +758,12 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         const uint32_t pitchb = (uint32_t)a.pitch * es;
         const uint32_t planeb = (uint32_t)((size_t)a.plane * es);
         const uint32_t tile_off = (uint32_t)(a.ox + tx * kTileX) * es;  // 128-byte aligned
-        const LoaderOffsets lo = loader_offsets<T, TY, W, MODE>(a, tx * kTileX, tile_off, pitchb);
+        const LoaderOffsets lo = loader_offsets<T, TY, W, MODE, XH>(a, tx * kTileX, tile_off, pitchb);
         // ordinates k0 .. k0 + kSlots - 2 in flight before the first barrier
 #pragma unroll
         for (int d = 0; d < R::kSlots - 1; ++d)
             if (k0 + d < k1)
-                ring_issue<T, TY, W, MODE>(a, k0 + d, yw, lo, pitchb, planeb, lds.ring + d * R::kSlotBytes);
+                ring_issue<T, TY, W, MODE, XH>(a, k0 + d, yw, lo, pitchb, planeb, lds.ring + d * R::kSlotBytes);
         __syncthreads();
         int slot = 0;
         for (int k = k0; k < k1; ++k) {
@@ -649,8 +778,8 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
             // the slot of ordinate k - 1 is free now: ordinate k + kSlots - 1 goes there
             const int s_free = slot == 0 ? R::kSlots - 1 : slot - 1;
             if (k + R::kSlots - 1 < k1)
-                ring_issue<T, TY, W, MODE>(a, k + R::kSlots - 1, yw, lo, pitchb, planeb,
-                                           lds.ring + s_free * R::kSlotBytes);
+                ring_issue<T, TY, W, MODE, XH>(a, k + R::kSlots - 1, yw, lo, pitchb, planeb,
+                                               lds.ring + s_free * R::kSlotBytes);
             slot = slot == R::kSlots - 1 ? 0 : slot + 1;
         }
         __syncthreads();
@@ -680,6 +809,9 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         w.ge1 = (holds_e0 || holds_e1) ? (uint32_t)(a.ox + a.nx) * es : kDropOffset;
         w.ge2 = (holds_e0 || holds_e1) ? (uint32_t)(a.ox + a.nx + 1) * es : kDropOffset;
         w.ge_first = holds_e0;
+        w.xb_w = holds_w;
+        w.xb_e0 = holds_e0;
+        w.xb_e1 = holds_e1;
         w.ghost_wave = MODE != kQoiOnly && (__any(holds_w || holds_e0 || holds_e1) || w.y0 == 0 ||
                                             (w.y0 <= a.ny - 1 && a.ny - 1 < w.y0 + TY));
     }
@@ -744,11 +876,12 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
             __syncthreads();  // ordinate k's rows are in slot `slot`
             const char* sb = lds.ring + slot * R::kSlotBytes;
             float2 win[TY + 4], oldv[TY];
-            float4 halo[TY];
+            float4 halo[TY + XH];  // x-halo of window rows 2 - XH/2 .. TY + 1 + XH/2
 #pragma unroll
             for (int r = 0; r < TY + 4; ++r) win[r] = ring_read<T>(sb + (wave * TY + r) * R::kRowBytes, lane);
 #pragma unroll
-            for (int t = 0; t < TY; ++t) halo[t] = halo_read<T>(sb + R::kHaloOffset + (wave * TY + t) * R::kHaloRowBytes);
+            for (int t = 0; t < TY + XH; ++t)
+                halo[t] = halo_read<T>(sb + R::kHaloOffset + (wave * TY + t) * R::kHaloRowBytes);
 #pragma unroll
             for (int t = 0; t < TY; ++t)
                 oldv[t] = MODE == kAverage ? ring_read<T>(sb + (R::kOldRow0 + wave * TY + t) * R::kRowBytes, lane)
@@ -789,7 +922,7 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
 template <int ORDER, int MODE, typename T, int TY, int W>
 __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_kernel(const StageArgs a) {
     extern __shared__ double facc_all[];  // [2 n_rects][kWave W] per-thread FP64 face accumulators
-    __shared__ StageLds<T, TY, W, MODE> lds;
+    __shared__ StageLds<T, TY, W, MODE, kExtraHalo<ORDER>> lds;
     stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, xcd_contiguous(blockIdx.x, gridDim.x), facc_all, lds);
 }
 
@@ -836,7 +969,7 @@ __device__ __forceinline__ InstanceRef find_instance(const int32_t* first, const
 template <int ORDER, int MODE, typename T, int TY, int W>
 __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_batch_kernel(const BatchLaunch L) {
     extern __shared__ double facc_all[];
-    __shared__ StageLds<T, TY, W, MODE> lds;
+    __shared__ StageLds<T, TY, W, MODE, kExtraHalo<ORDER>> lds;
     __shared__ int inst[2];
     const int pos = xcd_contiguous(blockIdx.x, gridDim.x);
     for (int base = 0; base < L.total; base += gridDim.x) {

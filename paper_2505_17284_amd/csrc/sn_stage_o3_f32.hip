@@ -1,0 +1,15 @@
+// Stage kernels for order 3 (Venkatakrishnan), psi stored as f32 (instantiations of sn_stage_impl.h).
+#include "sn_stage_impl.h"
+
+namespace snk {
+
+hipError_t launch_stage_o3_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s) {
+    return launch_stage_tu<3, float>(mode, rows, waves, a, s);
+}
+
+hipError_t launch_batch_o3_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
+                               int max_rects, hipStream_t s) {
+    return launch_batch_tu<3, float>(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
+}
+
+}  // namespace snk

@@ -63,7 +63,7 @@ sn_status check_opts(const sn_batch_opts* o) {
         return fail(SN_ERR_INVALID, "max_instances = %d out of range [1, 4096]", o->max_instances);
     if (o->max_steps_per_run < 1 || o->max_steps_per_run > 256)
         return fail(SN_ERR_INVALID, "max_steps_per_run = %d out of range [1, 256]", o->max_steps_per_run);
-    if (o->order != 1 && o->order != 2) return fail(SN_ERR_INVALID, "order must be 1 or 2");
+    if (o->order < 1 || o->order > 3) return fail(SN_ERR_INVALID, "order must be 1, 2 or 3");
     if (o->stepper != SN_EULER && o->stepper != SN_HEUN) return fail(SN_ERR_INVALID, "stepper must be Euler or Heun");
     if (o->psi_dtype != SN_F32 && o->psi_dtype != SN_BF16) return fail(SN_ERR_INVALID, "psi_dtype must be F32 or BF16");
     const int rows = o->rows_per_wave ? o->rows_per_wave : 2;

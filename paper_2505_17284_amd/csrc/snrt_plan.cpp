@@ -61,7 +61,7 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     if (p->n_rects < 0 || p->n_rects > SN_MAX_RECTS)
         return fail(SN_ERR_INVALID, "n_rects = %d out of range [0, %d]", p->n_rects, SN_MAX_RECTS);
     if (p->n_rects > 0 && !p->rects) return fail(SN_ERR_INVALID, "rects is NULL");
-    if (p->order != 1 && p->order != 2) return fail(SN_ERR_INVALID, "order must be 1 or 2");
+    if (p->order < 1 || p->order > 3) return fail(SN_ERR_INVALID, "order must be 1, 2 or 3");
     if (p->stepper != SN_EULER && p->stepper != SN_HEUN) return fail(SN_ERR_INVALID, "stepper must be Euler or Heun");
     if (p->psi_dtype != SN_F32 && p->psi_dtype != SN_BF16) return fail(SN_ERR_INVALID, "psi_dtype must be F32 or BF16");
     if (p->fluence != 0 && p->fluence != 1) return fail(SN_ERR_INVALID, "fluence must be 0 or 1");
@@ -396,6 +396,10 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
     for (int s = 0; s < 4; ++s) a.bc[s] = P->bc[s];
     for (int r = 0; r < P->n_rects; ++r)
         for (int e = 0; e < 4; ++e) a.rect[r][e] = P->rects[r][e];
+    {
+        const double A = P->h * P->h, eps = A * A * A;  // K A^3 with K = 1 (Sec. 4.2)
+        a.eps2 = (float)(eps * eps);
+    }
     return a;
 }
 
@@ -460,6 +464,7 @@ GhostArgs ghost_args(const sn_plan* P, char* psi) {
         ga.bc[side] = P->bc[side];
         ga.ghost[side] = P->bc[side] == SN_BC_INFLOW ? (float)P->inflow[side] : 0.0f;
     }
+    ga.all_dirs = P->order == 3 ? 1 : 0;
     return ga;
 }
 

@@ -65,7 +65,7 @@ def test_valid_problems_accepted(L):
 
 @pytest.mark.parametrize("field,value,needle", [
     ("cfl", 0.0, "cfl"), ("cfl", float("nan"), "cfl"), ("t_end", -1.0, "t_end"),
-    ("h", 0.0, "cell size"), ("nx", 0, "grid"), ("order", 3, "order"), ("stepper", 2, "stepper"),
+    ("h", 0.0, "cell size"), ("nx", 0, "grid"), ("order", 4, "order"), ("stepper", 2, "stepper"),
     ("n_tallies", 9, "n_tallies"), ("n_rects", 5, "n_rects"), ("psi_dtype", 7, "psi_dtype"),
     ("M", 0, "M ="), ("n_regions", 0, "n_regions"),
 ])

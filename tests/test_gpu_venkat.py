@@ -1,0 +1,103 @@
+"""Order 3 on the GPU (the Green-Gauss gradient with the Venkatakrishnan
+limiter, Sec. 4.2, eq. eq_V_limiter) through the C ABI, against the FP64
+oracle: random states on ragged grids with every boundary kind and both
+steppers, degenerate and tile-edge shapes, every launch shape, BF16 storage,
+a full lattice run, and batch members bit-identical to the plan alone."""
+
+import numpy as np
+import pytest
+
+from paper_2505_17284_amd import inputs as I
+from tests.test_gpu_parity import BCS, _check, _run_both
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17284_amd import solver
+
+    return solver
+
+
+@pytest.mark.parametrize("stepper", [I.EULER, I.HEUN])
+@pytest.mark.parametrize("bc", list(BCS))
+def test_random_state_few_steps(sv, orc, stepper, bc):
+    """130 x 37 (3 x-tiles, partial y-tiles), 2 steps: every element of psi
+    and phi and every QoI; reflective sides exercise the mirrors' ghosts."""
+    b, g = BCS[bc]
+    p = I.random_materials(130, 37, 5, seed=30 + stepper, order=3, stepper=stepper,
+                           bc=b, inflow=g, M=32, h=0.05, t_end=1.0)
+    psi0 = I.random_state(p, 1234, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0)
+    _check(p, g_, o_, 2)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (61, 17), (64, 64), (129, 5)])
+def test_degenerate_and_tile_edge_shapes(sv, orc, shape):
+    nx, ny = shape
+    rects = [(0, 0, nx, ny)]
+    if nx >= 3 and ny >= 3:
+        rects.append((1, 1, nx - 1, ny - 1))
+    p = I.random_materials(nx, ny, 3, seed=nx * 100 + ny, order=3, stepper=I.HEUN,
+                           bc=BCS["mixed"][0], inflow=BCS["mixed"][1], M=32, h=0.1, rects=rects)
+    psi0 = I.random_state(p, 77, "uniform")
+    g_, o_ = _run_both(sv, orc, p, 3, psi0=psi0)
+    _check(p, g_, o_, 3)
+
+
+@pytest.mark.parametrize("rows,waves", [(2, 4), (4, 4), (2, 8), (4, 8)])
+def test_launch_shapes_agree(sv, orc, rows, waves):
+    p = I.random_materials(200, 70, 4, seed=5, order=3, stepper=I.HEUN, bc=BCS["reflect"][0],
+                           inflow=BCS["reflect"][1], M=32, h=0.05)
+    psi0 = I.random_state(p, 9, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0, group_size=5, rows_per_wave=rows, waves_per_group=waves)
+    _check(p, g_, o_, 2)
+
+
+def test_bf16_storage(sv, orc):
+    """BF16 storage with stochastic rounding: each stored value is within one
+    bfloat16 ulp (2^-8 relative at most), so four stages stay within a few
+    2^-8 of the local magnitude (the bound of the other orders' BF16 test)."""
+    from tests.parity import compare_field
+
+    p = I.random_materials(130, 37, 5, seed=3, order=3, stepper=I.HEUN, M=32, h=0.05, psi_dtype="bf16")
+    psi0 = I.random_state(p, 5, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0)
+    ok, rep = compare_field(g_["psi"], o_["psi"], 4, rtol=4 * 2.0 ** -8, atol_scale=2.0 ** -8)
+    print(rep)
+    assert ok, rep
+
+
+def test_lattice_full_run(sv, orc):
+    """Lattice 140^2, 64 ordinates, Heun, to T = 3.2 (128 steps)."""
+    p = I.lattice(140, 64, order=3, stepper=I.HEUN)
+    g_, o_ = _run_both(sv, orc, p, None)
+    _check(p, g_, o_, o_["nt"])
+
+
+@pytest.mark.parametrize("stepper", [I.EULER, I.HEUN])
+def test_batch_bit_identical_to_alone(sv, stepper):
+    from paper_2505_17284_amd import batch
+
+    probs = [I.lattice(70, 32, order=3, stepper=stepper, t_end=0.4),
+             I.random_materials(61, 17, 4, seed=1, M=64, order=3, stepper=stepper,
+                                bc=(I.BC_REFLECT, I.BC_INFLOW, I.BC_INFLOW, I.BC_REFLECT),
+                                inflow=(0.0, 0.7, 0.3, 0.0), t_end=0.3)]
+    alone = [sv.solve(p, return_psi=True, rows_per_wave=2, waves_per_group=4) for p in probs]
+    print(f"[case] order-3 batch stepper={stepper}", flush=True)
+    b = batch.Batch(order=3, stepper=stepper, max_instances=4, steps_per_run=5)
+    try:
+        slots = [b.admit(p) for p in probs]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            r = b.result(s, psi=True)
+            assert np.array_equal(r["psi"], a["psi"]), p.name
+            assert r["qoi"] == a["qoi"] and r["qoi_int"] == a["qoi_int"], p.name
+    finally:
+        b.close()
