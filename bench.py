@@ -150,6 +150,15 @@ def time_tessellation(steps, dtype, N=22, warmup=2):
     return time_workload(p, f"lattice700_tess{N}_M{4 * N * N}_heun2", steps, warmup)
 
 
+def time_venkat(steps, dtype, warmup=2):
+    """The benchmark lattice (700^2, 256 ordinates, Heun) with the paper's own
+    limiter: the Green-Gauss gradient with the Venkatakrishnan limiter (order 3)."""
+    from paper_2505_17284_amd import inputs as I
+
+    p = I.config(2).replace(order=3, psi_dtype=dtype, name="lattice700_M256_venkat")
+    return time_workload(p, "lattice700_M256_heun_venkat", steps, warmup)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +181,9 @@ def main():
     ap.add_argument("--tess-steps", type=int, default=10,
                     help="Heun steps timed on the 700^2 lattice with the tessellation quadrature, "
                          "N = 22 (1936 ordinates; 0 skips it)")
+    ap.add_argument("--venkat-steps", type=int, default=40,
+                    help="Heun steps timed on the benchmark lattice with the Venkatakrishnan limiter "
+                         "(order 3; 0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -262,6 +274,8 @@ def main():
         line["cavity"] = time_cavity(args.cavity_steps, args.dtype)
     if args.tess_steps:
         line["tessellation"] = time_tessellation(args.tess_steps, args.dtype)
+    if args.venkat_steps:
+        line["venkat"] = time_venkat(args.venkat_steps, args.dtype)
     from paper_2505_17284_amd import serve
 
     if args.uq:

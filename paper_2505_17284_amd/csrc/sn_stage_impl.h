@@ -170,14 +170,21 @@ __device__ __forceinline__ float minmod(float a, float b) {
     return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
 }
 
-// Order 3 (Sec. 4.2, eq. eq_V_limiter): the Venkatakrishnan factor of one
-// face, whose reconstruction increment is d, with b_max = max - c and b_min
-// = min - c over the cell and its four neighbours; 1 where d = 0.
-__device__ __forceinline__ float venkat_face(float d, float bmax, float bmin, float e2) {
-    const float b = d > 0.0f ? bmax : bmin;
-    const float num = fmaf(2.0f * d, b, fmaf(b, b, e2));
-    const float den = fmaf(b, d, fmaf(2.0f * d, d, fmaf(b, b, e2)));
-    return d == 0.0f ? 1.0f : num / den;
+// Order 3 (Sec. 4.2, eq. eq_V_limiter). The limiter's factor of a face with
+// reconstruction increment d is (b^2 + e^2 + 2 d b) / (b^2 + 2 d^2 + b d + e^2)
+// with b = max - c for d > 0 and b = min - c for d < 0 (max, min over the cell
+// and its four neighbours), and 1 for d = 0. The two faces of one direction
+// have increments +A and -A (A = |increment|); negating both d and b leaves
+// the factor unchanged, so they are the factors of A with b_up = max - c and
+// b_dn = c - min, both >= 0. The quotient uses the hardware reciprocal
+// (within 1 ulp): the factor only scales an increment, so its last bit is far
+// below the FP32 error of the stage.
+__device__ __forceinline__ float venkat_pair(float A, float b_up, float b_dn, float e2) {
+    const float a2 = 2.0f * A * A;
+    const float qu = fmaf(b_up, b_up, e2), qd = fmaf(b_dn, b_dn, e2);
+    const float fu = fmaf(2.0f * A, b_up, qu) * __builtin_amdgcn_rcpf(fmaf(A, b_up, qu + a2));
+    const float fd = fmaf(2.0f * A, b_dn, qd) * __builtin_amdgcn_rcpf(fmaf(A, b_dn, qd + a2));
+    return A == 0.0f ? 1.0f : fminf(fu, fd);
 }
 
 // The limited reconstruction of a cell with value c and neighbours W, E, S,
@@ -192,9 +199,8 @@ __device__ __forceinline__ float venkat_limit(float c, float W, float E, float S
     ay = 0.25f * (N - S);
     const float mx = fmaxf(fmaxf(fmaxf(W, E), fmaxf(S, N)), c);
     const float mn = fminf(fminf(fminf(W, E), fminf(S, N)), c);
-    const float bmax = mx - c, bmin = mn - c;
-    return fminf(fminf(venkat_face(ax, bmax, bmin, e2), venkat_face(-ax, bmax, bmin, e2)),
-                 fminf(venkat_face(ay, bmax, bmin, e2), venkat_face(-ay, bmax, bmin, e2)));
+    const float b_up = mx - c, b_dn = c - mn;
+    return fminf(venkat_pair(fabsf(ax), b_up, b_dn, e2), venkat_pair(fabsf(ay), b_up, b_dn, e2));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -530,9 +536,10 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
     // cells 0 and 1), first order on the grid's boundary faces.
     float xw[TY], xe0[TY], xe1[TY];
     if (ORDER == 3) {
-        // halo[h] is the x-halo of window row h + 1
+        // halo[h] is the x-halo of window row h + 1. Rows 1 + D .. TY + 1 + D
+        // hold every upwind cell of the output rows' faces.
 #pragma unroll
-        for (int r = 1; r <= TY + 2; ++r) {
+        for (int r = 1 + D; r <= TY + 1 + D; ++r) {
             const float c0 = win[r].x, c1 = win[r].y;
             const float4 hv = halo[r - 1];               // cells -2, -1, 128, 129 of window row r
             const float lf = lane_from_left(c1, hv.y);   // cell left of c0
@@ -540,7 +547,7 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
             float ax0, ay0, ax1, ay1;
             const float L0 = venkat_limit(c0, lf, c1, win[r - 1].x, win[r + 1].x, a.eps2, ax0, ay0);
             const float L1 = venkat_limit(c1, c0, rt, win[r - 1].y, win[r + 1].y, a.eps2, ax1, ay1);
-            if (r >= 1 + D && r <= TY + 1 + D) {
+            {
                 // downwind y-face of row r; on the grid's boundary faces (south
                 // of row 0, north of row ny-1) the upwind cell's own value
                 const int gy = w.y0 - 2 + r;

@@ -225,8 +225,11 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
     // vs 2.69 ms with 1936. On grids of more than 2^20 cells the finalize's
     // extra phi partials (one plane per group) cost more than that gains
     // (the 1300 x 1300 x 512 cavity: 4.16 vs 4.22 ms per step). With BF16
-    // storage the halving measured slower (368 vs 330 us on the lattice).
-    const bool halve = *group_size >= 32 && P->dtype == SN_F32 && (int64_t)P->nx * P->ny <= (1 << 20);
+    // storage the halving measured slower (368 vs 330 us on the lattice), and
+    // with the Venkatakrishnan limiter (order 3), whose stage is bound by its
+    // arithmetic rather than by the copies in flight, too (572 vs 533 us).
+    const bool halve = *group_size >= 32 && P->dtype == SN_F32 && P->order < 3 &&
+                       (int64_t)P->nx * P->ny <= (1 << 20);
     *group_size_avg = halve ? (*group_size + 1) / 2 : *group_size;
 }
 
