@@ -164,10 +164,10 @@ __device__ __forceinline__ float lane_from_right(float x, float edge) {
 }
 
 // minmod(a, b): the argument of smaller magnitude when both have the same
-// strict sign, else 0. Exactly one of the two terms is non-zero, so the sum
-// is exact.
+// strict sign, else 0 -- which is the median of a, b and 0 (one v_med3_f32;
+// it returns one of its operands exactly).
 __device__ __forceinline__ float minmod(float a, float b) {
-    return fmaxf(fminf(a, b), 0.0f) + fminf(fmaxf(a, b), 0.0f);
+    return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
 // Order 3 (Sec. 4.2, eq. eq_V_limiter). The limiter's factor of a face with
