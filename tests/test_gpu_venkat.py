@@ -101,3 +101,37 @@ def test_batch_bit_identical_to_alone(sv, stepper):
             assert r["qoi"] == a["qoi"] and r["qoi_int"] == a["qoi_int"], p.name
     finally:
         b.close()
+
+
+def test_hohlraum_with_probes_and_fluence(sv, orc):
+    """The Hohlraum (n = 104, 64 Heun steps to t = 0.4) with the limiter, the paper's
+    four probes and the fluence: every QoI-1 window, every fluence element
+    and the green-band functionals against the oracle."""
+    from oracle import hohlraum_qoi
+
+    from paper_2505_17284_amd import hohlraum
+    from tests.parity import compare_field
+
+    p = I.hohlraum(104, 32, order=3, t_end=0.4)
+    print("[case] order-3 hohlraum probes + fluence", flush=True)
+    plan = sv.Plan(p, probes=hohlraum.probe_cells(p), fluence=True)
+    try:
+        plan.run()
+        g_probes, g_fl = plan.probes(), plan.fluence()
+        g_band = hohlraum.green_band_qois(plan)
+    finally:
+        plan.close()
+    o = orc.solve(p, fluence=True, probes=hohlraum_qoi.probe_cells(p))
+    ok, rep = compare_field(g_fl, o["fluence"], 2 * o["nt"])
+    print("fluence:", rep)
+    assert ok, rep
+    # per probe its largest window phi, floored at 1e-6 of the largest over
+    # all probes (the two probes beside the capsule see ~1e-16 by t = 0.4)
+    scale = np.abs(o["probes"][:, :, 0]).max(axis=0)
+    scale = np.maximum(scale, 1e-6 * scale.max())
+    assert np.all(np.abs(g_probes - o["probes"]) <= 1e-5 * np.abs(o["probes"]) + 1e-5 * scale[None, :, None])
+    ob = hohlraum_qoi.qois(p, o["fluence"])
+    for k in ("A_G", "A_L"):
+        assert g_band[k] == pytest.approx(ob[k], rel=1e-5)
+    for k, m in (("V_G", "A_G"), ("V_L", "A_L")):
+        assert abs(g_band[k] - ob[k]) <= 1e-5 * (abs(ob[k]) + ob[m] ** 2)
