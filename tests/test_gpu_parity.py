@@ -297,3 +297,26 @@ def test_tessellation_quadrature_random_state(sv, orc, N, order):
     psi0 = I.random_state(p, 31 + N)
     g, o = _run_both(sv, orc, p, 2, psi0=psi0)
     _check(p, g, o, 2)
+
+
+def test_full_size_tessellation22_random_state(sv, orc):
+    """The 700^2 lattice with the tessellation quadrature at N = 22 (1936
+    ordinates, 3.8 GB per psi buffer) in the launch shape the bench times:
+    one Heun step from a random state, sampled psi, all of phi and every QoI
+    against the oracle."""
+    p = I.lattice(700, order=2, stepper=I.HEUN, quad=I.tessellation_quadrature(22))
+    psi0 = I.random_state(p, 2222, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 1, psi0=psi0)
+    del psi0
+    oi, oint = _orc_dicts(o_)
+    ok, rep = compare_qoi(g_["qoi"], g_["qoi_int"], oi, oint)
+    print(rep)
+    assert ok, rep
+    rng = np.random.Generator(np.random.PCG64(4))
+    idx = tuple(rng.integers(0, s, 50000) for s in o_["psi"].shape)
+    okf, repf = compare_field(g_["psi"][idx], o_["psi"][idx], 2)
+    print("sampled psi:", repf)
+    assert okf, repf
+    okp, repp = compare_field(g_["phi"], o_["phi"], 2)
+    print("phi:", repp)
+    assert okp, repp

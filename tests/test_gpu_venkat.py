@@ -135,3 +135,27 @@ def test_hohlraum_with_probes_and_fluence(sv, orc):
         assert g_band[k] == pytest.approx(ob[k], rel=1e-5)
     for k, m in (("V_G", "A_G"), ("V_L", "A_L")):
         assert abs(g_band[k] - ob[k]) <= 1e-5 * (abs(ob[k]) + ob[m] ** 2)
+
+
+def test_full_size_lattice700_random_state(sv, orc):
+    """The limiter on the benchmark lattice at full size (700^2 cells, 256
+    ordinates, Heun) in the launch shape the bench times: one step from a
+    random state, sampled psi, all of phi and every QoI against the oracle."""
+    from tests.parity import compare_field, compare_qoi
+    from tests.test_gpu_parity import _orc_dicts
+
+    p = I.config(2).replace(order=3)
+    psi0 = I.random_state(p, 2025, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 1, psi0=psi0)
+    oi, oint = _orc_dicts(o_)
+    ok, rep = compare_qoi(g_["qoi"], g_["qoi_int"], oi, oint)
+    print(rep)
+    assert ok, rep
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = tuple(rng.integers(0, s, 20000) for s in o_["psi"].shape)
+    okf, repf = compare_field(g_["psi"][idx], o_["psi"][idx], 2)
+    print("sampled psi:", repf)
+    assert okf, repf
+    okp, repp = compare_field(g_["phi"], o_["phi"], 2)
+    print("phi:", repp)
+    assert okp, repp
