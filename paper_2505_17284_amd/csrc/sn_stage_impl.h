@@ -298,8 +298,10 @@ struct WaveCtx {
 // counters are per wave). The depth is set by the latency of a copy under
 // full load (several microseconds), not by its bytes: the stages without
 // psi^n rows keep 4 ordinates in flight, the averaging stage, whose slots
-// are almost twice as large, 2, both in ~32 KB of LDS per workgroup (4
-// workgroups per compute unit).
+// are almost twice as large, 2, both in ~32 KB of LDS per workgroup, plus
+// 2 n_rects FP64 face accumulators per thread (4 workgroups per compute unit
+// with at most one rectangle, 3 with the lattice's three; measured the same
+// speed).
 #ifndef SN_RING_SLOTS
 #define SN_RING_SLOTS 3
 #endif
