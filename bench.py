@@ -150,6 +150,38 @@ def time_tessellation(steps, dtype, N=22, warmup=2):
     return time_workload(p, f"lattice700_tess{N}_M{4 * N * N}_heun2", steps, warmup)
 
 
+def time_hohlraum(steps, dtype, n=1300, M=256, warmup=2):
+    """The Hohlraum (Sec. 3.2.1) at n^2 cells with every QoI on: the four
+    probes' windows (QoI-1) and the fluence behind QoI-3 to QoI-6, timed
+    against the same solve without them."""
+    import torch
+
+    from paper_2505_17284_amd import hohlraum
+    from paper_2505_17284_amd import inputs as I
+    from paper_2505_17284_amd import solver
+
+    p = I.hohlraum(n, M, psi_dtype=dtype)
+    out = {"workload": f"hohlraum{n}_M{M}_heun2", "steps": steps}
+    for label, kw in (("plain", {}), ("with_qois", {"probes": hohlraum.probe_cells(p), "fluence": True})):
+        print(f"[bench] hohlraum {label}: {p.name} {steps} steps", file=sys.stderr, flush=True)
+        plan = solver.Plan(p, device="cuda:0", **kw)
+        try:
+            plan.run(warmup, unbounded=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.run(steps, unbounded=True)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            if kw:
+                out["green_band_A_G"] = hohlraum.green_band_qois(plan)["A_G"]
+        finally:
+            plan.close()
+        out[f"ms_per_step_{label}"] = secs * 1e3 / steps
+        out[f"updates_per_s_{label}"] = p.cell_ordinates * steps / secs
+    out["qoi_overhead"] = out["ms_per_step_with_qois"] / out["ms_per_step_plain"] - 1.0
+    return out
+
+
 def time_venkat(steps, dtype, warmup=2):
     """The benchmark lattice (700^2, 256 ordinates, Heun) with the paper's own
     limiter: the Green-Gauss gradient with the Venkatakrishnan limiter (order 3)."""
@@ -184,6 +216,9 @@ def main():
     ap.add_argument("--venkat-steps", type=int, default=40,
                     help="Heun steps timed on the benchmark lattice with the Venkatakrishnan limiter "
                          "(order 3; 0 skips it)")
+    ap.add_argument("--hohlraum-steps", type=int, default=20,
+                    help="Heun steps timed on the 1300^2 x 256 Hohlraum with and without its probes and "
+                         "fluence (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -276,6 +311,8 @@ def main():
         line["tessellation"] = time_tessellation(args.tess_steps, args.dtype)
     if args.venkat_steps:
         line["venkat"] = time_venkat(args.venkat_steps, args.dtype)
+    if args.hohlraum_steps:
+        line["hohlraum"] = time_hohlraum(args.hohlraum_steps, args.dtype)
     from paper_2505_17284_amd import serve
 
     if args.uq:

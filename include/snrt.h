@@ -39,7 +39,7 @@ extern "C" {
 #define SN_MAX_TALLIES 8   /* absorption tally regions */
 #define SN_MAX_RECTS 4     /* outflow/inflow rectangles */
 #define SN_MAX_FLUENCE_BLOCKS 1024 /* blocks of sn_plan_fluence_functionals */
-#define SN_MAX_PROBES 16             /* space-time probes */
+#define SN_MAX_PROBES 8              /* space-time probes */
 #define SN_MAX_WINDOWS 4096          /* time windows of the probes */
 #define SN_MAX_PROBE_CELLS (1 << 20) /* cells of all probes together */
 #define SN_MAX_REGIONS 256 /* material regions (uint8 ids) */
@@ -111,6 +111,12 @@ typedef struct sn_probe_cell {
  *                 0 <= n_probes <= SN_MAX_PROBES; 1 <= n_windows <=
  *                 SN_MAX_WINDOWS when n_probes > 0; probe_cells[n_probe_cells]
  *                 (n_probe_cells <= SN_MAX_PROBE_CELLS) may be NULL when 0.
+ *                 The stage kernels sum the probes over tiles of 128 columns
+ *                 by rows_per_wave x waves rows (8 by default): plan creation
+ *                 fails with SN_ERR_UNSUPPORTED when a tile holds more probe
+ *                 cells than fit 64 lanes of 8, a lane's cells all of one
+ *                 probe (at least 448 fit: in the default 8-row tiles, the
+ *                 cells of one ball of radius 30 h).
  *  fluence        1: also accumulate the fluence Phi = int_0^t phi dt per cell
  *                 in FP64, with the stepper's time rule (Euler dt phi(psi^n);
  *                 Heun dt/2 (phi(psi^n) + phi(psi^(1)))); the Hohlraum QoI-3

@@ -31,7 +31,7 @@ MAX_FLUENCE_BLOCKS = 1024
 FLUENCE_PIECE = np.dtype([("cell_a", np.int32), ("cell_b", np.int32), ("weight", np.float64)])
 # sn_probe_cell: interior cell index, probe id, the cell's weight in the probe's average
 PROBE_CELL = np.dtype([("cell", np.int32), ("probe", np.int32), ("weight", np.float64)])
-MAX_PROBES = 16
+MAX_PROBES = 8
 
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = [

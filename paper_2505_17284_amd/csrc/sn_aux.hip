@@ -91,8 +91,8 @@ __global__ void __launch_bounds__(256) sn_ghost_fill_kernel(const GhostArgs a) {
 // Workgroups [nq, nq + n_phi_wg): phi = sum over groups of the stage's
 // partial scalar fluxes, in group order, for every interior cell (4 padded
 // columns per thread, ny * pitch / 4 threads), first adding the replaced phi
-// (the stage input's) to the fluence when that is kept. Workgroups
-// [nq + n_phi_wg, + n_probes): one per space-time probe.
+// (the stage input's) to the fluence when that is kept. The QoI slots of the
+// space-time probes also accumulate into the window of the current step.
 using FArgs = const __attribute__((address_space(4))) FinalizeArgs&;
 using FArgsPtr = const __attribute__((address_space(4))) FinalizeArgs*;
 
@@ -107,48 +107,7 @@ __device__ double block_sum(double v, double* red) {
     return red[0];
 }
 
-// Probe p: phi, J_x, J_y of the stage input over the probe's weighted cells,
-// added with the stage's time weight to the window the step falls in. Each
-// probe block owns its step counter, so reading and advancing it need no
-// coordination with other blocks.
-__device__ void probe_block(FArgs a, int p) {
-    __shared__ double red[256];
-    const int32_t step = a.pstep[p];
-    __syncthreads();  // every thread has read the counter before thread 0 advances it
-    const int64_t w = (int64_t)step * a.n_windows / a.nt;
-    if (w < a.n_windows) {
-        const int c0 = a.pstart[p], nc = a.pstart[p + 1] - c0;
-        const int M = a.M;
-        double m0 = 0.0, mx = 0.0, my = 0.0;
-        for (int64_t u = threadIdx.x; u < (int64_t)nc * M; u += 256) {
-            const int c = (int)(u / M), k = (int)(u - (int64_t)c * M);
-            const ProbeCell pc = a.pcell[c0 + c];
-            const int64_t e = (int64_t)k * a.plane + pc.off;
-            const float x = a.dtype == 0 ? static_cast<const float*>(a.psi_in)[e]
-                                         : bf16_widen(static_cast<const uint16_t*>(a.psi_in)[e]);
-            const double v = pc.weight * (double)x;
-            m0 += a.pmom[3 * k] * v;
-            mx += a.pmom[3 * k + 1] * v;
-            my += a.pmom[3 * k + 2] * v;
-        }
-        const double s0 = block_sum(m0, red);
-        const double sx = block_sum(mx, red);
-        const double sy = block_sum(my, red);
-        if (threadIdx.x == 0) {
-            double* acc = a.pacc + (w * a.n_probes + p) * 3;
-            acc[0] += a.pcoef * s0;
-            acc[1] += a.pcoef * sx;
-            acc[2] += a.pcoef * sy;
-        }
-    }
-    if (threadIdx.x == 0 && a.last_stage) a.pstep[p] = step + 1;
-}
-
 __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
-    if (blk >= a.nq + a.n_phi_wg) {
-        probe_block(a, blk - a.nq - a.n_phi_wg);
-        return;
-    }
     if (blk >= a.nq) {
         // four consecutive padded columns per thread (16-byte aligned: the
         // pitch is a multiple of 16 elements); only interior cells are written
@@ -227,6 +186,15 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
         a.integ[s] += a.coef * tot;
         if (!isfinite(tot)) a.flags[0] = 1;
         if (s == 0) a.counter[0] += 1;  // one finalize per stage; the next stage reads it
+        if (a.n_probes > 0 && s >= a.qprobe) {
+            // a probe moment: also into the window of the step (this block
+            // owns the slot's step counter)
+            const int q = s - a.qprobe;
+            const int32_t step = a.pstep[q];
+            const int64_t w = (int64_t)step * a.n_windows / a.nt;
+            if (w < a.n_windows) a.pacc[(w * a.n_probes + q / 3) * 3 + q % 3] += a.pcoef * tot;
+            if (a.last_stage) a.pstep[q] = step + 1;
+        }
     }
 }
 
@@ -356,7 +324,7 @@ hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq + a.n_phi_wg + a.n_probes), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq + a.n_phi_wg), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

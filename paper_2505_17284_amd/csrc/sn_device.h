@@ -28,9 +28,13 @@ constexpr int kTileX = kCellsPerLane * kWave;  // 128 output columns per wave (t
 constexpr int kGhost = 2;                      // ghost-frame width
 constexpr int kMaxTallies = 8;
 constexpr int kMaxRects = 4;
-constexpr int kMaxQ = 1 + kMaxTallies + 2 * kMaxRects;  // mass, absorption, out, in
+constexpr int kMaxProbes = 8;
+// mass, absorption per tally, outflow and inflow per rectangle (summed by the
+// compute waves), then phi, J_x, J_y per space-time probe (by the loader wave)
+constexpr int kMaxQWave = 1 + kMaxTallies + 2 * kMaxRects;
+constexpr int kMaxQ = kMaxQWave + 3 * kMaxProbes;
 constexpr int kMaxFluenceBlocks = 1024;
-constexpr int kMaxProbes = 16;
+constexpr int kProbePerLane = 8;  // probe cells one loader lane accumulates
 
 enum StageMode : int {
     kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)                   (Euler, Heun stage 1)
@@ -85,6 +89,21 @@ struct StageArgs {
     int32_t bc[4];
     int32_t rect[kMaxRects][4];
     float eps2;             // order 3: the limiter's epsilon^2, (h^2)^6
+    // space-time probes: the loader wave of tile t accumulates phi, J_x, J_y
+    // of the stage input over the tile's probe cells into QoI slots
+    // qprobe + 3 p + m (qprobe = 1 + n_tallies + 2 n_rects)
+    const struct ProbeEntry* pent;  // probe cells, grouped by tile, then by lane
+    const int32_t* ptile;           // [ntiles][3]: first entry, entries per lane, lanes
+    const double* pmom;             // [M][3] w, w xi, w eta in FP64
+    int32_t n_probes, qprobe;
+};
+
+// One probe cell as a loader lane reads it: byte offset of the cell in a ring
+// slot, its probe, and its weight (0 for padding).
+struct ProbeEntry {
+    uint32_t lds_off;
+    int32_t probe;  // -1: padding
+    double weight;
 };
 
 // One batched launch over several instances (plans): the grid strides over
@@ -133,23 +152,14 @@ struct FinalizeArgs {
     double coef;            // weight of this stage in the time integral
     int32_t n_wg, nq;
     double* fluence;        // [ny][nx] running time integral of phi, or NULL
-    // space-time probes: blocks [nq + n_phi_wg, + n_probes) each reduce one
-    // probe's moments of the stage input into its current time window
-    const void* psi_in;     // the stage input (dtype below), padded planes
-    const struct ProbeCell* pcell;  // [cells] sorted by probe
-    const int32_t* pstart;  // [n_probes + 1]
-    const double* pmom;     // [M][3] w, w xi, w eta in FP64
+    // space-time probes: QoI slots qprobe + 3 p + m (p probe, m = phi, J_x,
+    // J_y) also add pcoef times their total to the window of the current step
     double* pacc;           // [n_windows][n_probes][3]
-    int32_t* pstep;         // [n_probes] steps finished so far (one counter per probe block)
+    int32_t* pstep;         // [3 n_probes] steps finished so far, one counter per slot block
     double pcoef;           // coef / window length
-    int32_t n_probes;       // 0: no probe blocks in this launch
-    int32_t n_windows, nt, M, dtype;
+    int32_t n_probes;       // 0: no window accumulation in this launch
+    int32_t qprobe, n_windows, nt;
     int32_t last_stage;     // 1: this stage ends a step
-};
-
-struct ProbeCell {
-    int64_t off;  // the cell's offset in a padded plane
-    double weight;
 };
 
 // One piece of a block or line integral of sigma_a * fluence (the layout of

@@ -66,13 +66,15 @@ struct sn_plan {
     // functionals read: sigma_a in FP64 and a status word
     bool fluence = false;
     size_t off_fluence = 0, off_sa64 = 0, off_fstatus = 0;
-    // space-time probes: cells sorted by probe, their moments table, the
-    // window accumulators and the per-probe step counters
+    // space-time probes: the caller's cells, the loader waves' per-tile entry
+    // tables, the moments table, the window accumulators and the step
+    // counters of the probe QoI slots
     int n_probes = 0, n_windows = 0;
-    std::vector<snk::ProbeCell> pcell_h;
-    std::vector<int32_t> pstart_h;
-    std::vector<double> pmom_h;  // [M][3]
-    size_t off_pcell = 0, off_pstart = 0, off_pmom = 0, off_pacc = 0, off_pstep = 0;
+    std::vector<sn_probe_cell> pcell_h;
+    std::vector<snk::ProbeEntry> pent_h;
+    std::vector<int32_t> ptile_h;  // [ntiles][3]: first entry, entries per lane, lanes
+    std::vector<double> pmom_h;    // [M][3]
+    size_t off_pent = 0, off_ptile = 0, off_pmom = 0, off_pacc = 0, off_pstep = 0;
     double source = 0;  // (sum w) h^2 sum_cells Q
     std::vector<snk::OrdConst> ord_h;
     std::vector<snk::RegConst> reg_h;
@@ -113,9 +115,9 @@ namespace snh {
 // snrt_plan.cpp for the buffer roles of each kind). A stage with psi^n
 // (old != NULL) is Heun's averaging stage and takes that stage's layout.
 snk::StageArgs stage_args(const sn_plan* P, const char* in, const char* old, char* out);
-// Finalize arguments of a stage of P that read psi_in; kind 0 Euler, 1/2 Heun
-// stages, -1 QoI only.
-snk::FinalizeArgs finalize_args(const sn_plan* P, int kind, const char* psi_in);
+// Finalize arguments of a stage of P; kind 0 Euler, 1/2 Heun stages, -1 QoI
+// only.
+snk::FinalizeArgs finalize_args(const sn_plan* P, int kind);
 // Workgroups of that finalize.
 int finalize_workgroups(const sn_plan* P, int kind);
 // Issue n whole steps of P on s with plain launches (no graph, no timing);

@@ -752,9 +752,13 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nwg) {
 
 template <typename T, int TY, int W, int MODE, int XH>
 struct StageLds {
-    double red[W][kMaxQ];
+    double red[W][kMaxQWave];
+    double probe_red[kMaxProbes][3];  // the loader wave's probe moments
     alignas(16) char ring[Ring<T, TY, W, MODE, XH>::kBytes];
 };
+
+using const_f64_ptr = const __attribute__((address_space(4))) double*;
+using const_i32_ptr = const __attribute__((address_space(4))) int32_t*;
 
 // The work of logical workgroup `logical` of one stage launch: tile and
 // ordinate group, all ordinates of the group, epilogues. facc_all holds
@@ -783,6 +787,40 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         const uint32_t planeb = (uint32_t)((size_t)a.plane * es);
         const uint32_t tile_off = (uint32_t)(a.ox + tx * kTileX) * es;  // 128-byte aligned
         const LoaderOffsets lo = loader_offsets<T, TY, W, MODE, XH>(a, tx * kTileX, tile_off, pitchb);
+        // Space-time probes: between its copies the loader reads the tile's
+        // probe cells of every staged ordinate from LDS. Lane l holds entries
+        // pb + l pl .. pb + l pl + pl - 1, all of one probe (bit e of pvalid:
+        // entry e is a cell, not padding). They are loaded here, before any
+        // copy is in flight, so that waiting for them waits for no copy.
+        int pl = 0;
+        uint32_t poff[kProbePerLane];
+        double pwt[kProbePerLane];
+        uint32_t pvalid = 0;
+        int my_probe = -1;
+        double pm0 = 0.0, pm1 = 0.0, pm2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < kProbePerLane; ++e) {
+            poff[e] = 0;
+            pwt[e] = 0.0;
+        }
+        if (a.n_probes > 0) {
+            const const_i32_ptr pt = (const_i32_ptr)a.ptile + 3 * tile;
+            const int pb = pt[0];
+            pl = pt[1];
+            const int lanes = pt[2];
+#pragma unroll
+            for (int e = 0; e < kProbePerLane; ++e) {
+                if (e < pl && lane < lanes) {
+                    const ProbeEntry pe = a.pent[pb + lane * pl + e];
+                    if (pe.probe >= 0) {
+                        poff[e] = pe.lds_off;
+                        pwt[e] = pe.weight;
+                        pvalid |= 1u << e;
+                        my_probe = pe.probe;
+                    }
+                }
+            }
+        }
         // ordinates k0 .. k0 + kSlots - 2 in flight before the first barrier
 #pragma unroll
         for (int d = 0; d < R::kSlots - 1; ++d)
@@ -804,7 +842,39 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
             if (k + R::kSlots - 1 < k1)
                 ring_issue<T, TY, W, MODE, XH>(a, k + R::kSlots - 1, yw, lo, pitchb, planeb,
                                                lds.ring + s_free * R::kSlotBytes);
+            if (pl > 0) {  // workgroup-uniform
+                // w, w xi, w eta of ordinate k: scalar loads, which leave the
+                // copies' wait counter alone
+                const const_f64_ptr mk = (const_f64_ptr)a.pmom + 3 * k;
+                const double w0 = mk[0], w1 = mk[1], w2 = mk[2];
+                const char* sb = lds.ring + slot * R::kSlotBytes;
+                float x[kProbePerLane];  // all reads in flight together (padding reads cell 0)
+#pragma unroll
+                for (int e = 0; e < kProbePerLane; ++e)
+                    x[e] = sizeof(T) == 4 ? *reinterpret_cast<const float*>(sb + poff[e])
+                                          : bf16_widen(*reinterpret_cast<const uint16_t*>(sb + poff[e]));
+                double v = 0.0;
+#pragma unroll
+                for (int e = 0; e < kProbePerLane; ++e)
+                    if (pvalid >> e & 1u) v = fma(pwt[e], (double)x[e], v);
+                pm0 = fma(w0, v, pm0);
+                pm1 = fma(w1, v, pm1);
+                pm2 = fma(w2, v, pm2);
+            }
             slot = slot == R::kSlots - 1 ? 0 : slot + 1;
+        }
+        if (a.n_probes > 0) {  // per probe, the wave's sum in lane order
+            for (int p = 0; p < a.n_probes; ++p) {
+                const bool mine = my_probe == p;
+                const double v0 = wave_sum(mine ? pm0 : 0.0);
+                const double v1 = wave_sum(mine ? pm1 : 0.0);
+                const double v2 = wave_sum(mine ? pm2 : 0.0);
+                if (lane == 0) {
+                    lds.probe_red[p][0] = v0;
+                    lds.probe_red[p][1] = v1;
+                    lds.probe_red[p][2] = v2;
+                }
+            }
         }
         __syncthreads();
         return;
@@ -934,9 +1004,14 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
     }
     __syncthreads();
     if (tid < a.nq) {
-        double tot = red[0][tid];
+        double tot;
+        if (tid >= a.qprobe) {  // a probe moment, from the loader wave
+            tot = lds.probe_red[(tid - a.qprobe) / 3][(tid - a.qprobe) % 3];
+        } else {
+            tot = red[0][tid];
 #pragma unroll
-        for (int ww = 1; ww < W; ++ww) tot += red[ww][tid];
+            for (int ww = 1; ww < W; ++ww) tot += red[ww][tid];
+        }
         a.qpart[(size_t)tid * a.n_wg + logical] = tot;
     }
 }

@@ -200,10 +200,10 @@ sn_status sn_batch_admit(sn_batch* B, sn_plan* P, int32_t* slot) {
         sa[0] = stage_args(P, P->psi[0], nullptr, P->psi[1]);
         sa[1] = stage_args(P, P->psi[1], nullptr, P->psi[0]);
     }
-    // one finalize per stage-argument variant (it reads that variant's input)
+    // one finalize per stage-argument variant
     FinalizeArgs fa[2];
-    fa[0] = finalize_args(P, P->stepper == SN_HEUN ? 1 : 0, P->psi[0]);
-    fa[1] = finalize_args(P, P->stepper == SN_HEUN ? 2 : 0, P->psi[1]);
+    fa[0] = finalize_args(P, P->stepper == SN_HEUN ? 1 : 0);
+    fa[1] = finalize_args(P, P->stepper == SN_HEUN ? 2 : 0);
     HIP_TRY(hipMemcpy(B->ws + B->off_stage + (size_t)s * 2 * sizeof(StageArgs), sa, sizeof sa, hipMemcpyHostToDevice),
             "upload stage arguments");
     HIP_TRY(hipMemcpy(B->ws + B->off_final + (size_t)s * 2 * sizeof(FinalizeArgs), fa, sizeof fa, hipMemcpyHostToDevice),

@@ -178,19 +178,7 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
     P->n_probes = p->n_probes;
     P->n_windows = p->n_probes > 0 ? p->n_windows : 0;
     P->pcell_h.clear();
-    P->pstart_h.assign(P->n_probes + 1, 0);
-    if (P->n_probes > 0) {
-        // cells grouped by probe, in the caller's order within a probe; `off`
-        // holds the interior index here and becomes the padded-plane offset
-        // when the tables are uploaded
-        for (int q = 0; q < P->n_probes; ++q) {
-            P->pstart_h[q] = (int32_t)P->pcell_h.size();
-            for (int c = 0; c < p->n_probe_cells; ++c)
-                if (p->probe_cells[c].probe == q)
-                    P->pcell_h.push_back(ProbeCell{(int64_t)p->probe_cells[c].cell, p->probe_cells[c].weight});
-        }
-        P->pstart_h[P->n_probes] = (int32_t)P->pcell_h.size();
-    }
+    if (P->n_probes > 0) P->pcell_h.assign(p->probe_cells, p->probe_cells + p->n_probe_cells);
     P->cfl = p->cfl;
     P->t_end = p->t_end;
     return SN_OK;
@@ -233,6 +221,69 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
     *group_size_avg = halve ? (*group_size + 1) / 2 : *group_size;
 }
 
+// The stage kernels' loader wave of a tile reads the tile's probe cells from
+// its LDS ring (the stencil rows of every ordinate it stages) and sums
+// w_k weight psi_k, w_k xi_k weight psi_k and w_k eta_k weight psi_k, in FP64.
+// Per tile: the cells grouped by probe (caller's order within a probe), dealt
+// pl to a lane, a lane's cells all of one probe (the last lane of a probe
+// padded), pl the smallest that fits the tile's cells into one wave.
+sn_status probe_tables(sn_plan* P) {
+    const int ntiles = P->ntx * P->nty;
+    const int tile_rows = P->waves * P->rows;
+    P->ptile_h.assign((size_t)3 * ntiles, 0);
+    P->pent_h.clear();
+    if (P->n_probes == 0) return SN_OK;
+    const int n = (int)P->pcell_h.size();
+    std::vector<int64_t> key(n);
+    std::vector<int32_t> idx(n);
+    for (int c = 0; c < n; ++c) {
+        const sn_probe_cell& pc = P->pcell_h[c];
+        const int j = pc.cell / P->nx, i = pc.cell - j * P->nx;
+        const int tile = (j / tile_rows) * P->ntx + i / kTileX;
+        key[c] = (int64_t)tile * P->n_probes + pc.probe;
+        idx[c] = c;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+    for (int b = 0; b < n;) {
+        const int tile = (int)(key[idx[b]] / P->n_probes);
+        int e = b;
+        while (e < n && key[idx[e]] / P->n_probes == tile) ++e;
+        int cnt[kMaxProbes] = {};
+        for (int c = b; c < e; ++c) cnt[P->pcell_h[idx[c]].probe]++;
+        int pl = 0, lanes = 0;
+        for (int cand = 1; cand <= kProbePerLane && pl == 0; ++cand) {
+            int l = 0;
+            for (int q = 0; q < P->n_probes; ++q) l += (cnt[q] + cand - 1) / cand;
+            if (l <= kWave) {
+                pl = cand;
+                lanes = l;
+            }
+        }
+        if (pl == 0)
+            return fail(SN_ERR_UNSUPPORTED,
+                        "%d probe cells in the tile of columns %d.. and rows %d..: at most %d per tile (%d lanes of "
+                        "%d, a lane's cells of one probe)",
+                        e - b, (tile % P->ntx) * kTileX, (tile / P->ntx) * tile_rows, kWave * kProbePerLane, kWave,
+                        kProbePerLane);
+        P->ptile_h[3 * tile] = (int32_t)P->pent_h.size();
+        P->ptile_h[3 * tile + 1] = pl;
+        P->ptile_h[3 * tile + 2] = lanes;
+        for (int c = b; c < e;) {  // one probe's cells
+            const int q = P->pcell_h[idx[c]].probe;
+            int m = 0;
+            for (; c < e && P->pcell_h[idx[c]].probe == q; ++c, ++m) {
+                const sn_probe_cell& pc = P->pcell_h[idx[c]];
+                const int j = pc.cell / P->nx, i = pc.cell - j * P->nx;
+                const uint32_t off = (uint32_t)(((j % tile_rows) + kGhost) * kTileX + i % kTileX) * (uint32_t)P->elem;
+                P->pent_h.push_back(ProbeEntry{off, q, pc.weight});
+            }
+            for (; m % pl != 0; ++m) P->pent_h.push_back(ProbeEntry{0u, -1, 0.0});
+        }
+        b = e;
+    }
+    return SN_OK;
+}
+
 sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int waves) {
     // dt = CFL * h (Sec. 5.1.3), adjusted so that N_t dt = T (Sec. 4.3).
     const double r = P->t_end / (P->cfl * P->h);
@@ -272,7 +323,11 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     if (n_wg > (int64_t)0x7fffffff) return fail(SN_ERR_UNSUPPORTED, "too many workgroups");
     P->n_wg = (int)n_wg;
     for (int l = 0; l < 2; ++l) P->n_wg_l[l] = P->ntx * P->nty * P->G_l[l];
-    P->nq = 1 + P->n_tallies + 2 * P->n_rects;
+    P->nq = 1 + P->n_tallies + 2 * P->n_rects + 3 * P->n_probes;
+    {
+        const sn_status st = probe_tables(P);
+        if (st != SN_OK) return st;
+    }
 
     P->psi_bytes = align256((size_t)P->M * (size_t)P->plane * P->elem);
     size_t off = 0;
@@ -304,22 +359,22 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     off += align256(sizeof(int32_t));
     P->off_fluence = off;
     if (P->fluence) off += align256((size_t)P->nx * P->ny * sizeof(double));
-    P->off_pcell = off;
-    P->off_pstart = off;
+    P->off_pent = off;
+    P->off_ptile = off;
     P->off_pmom = off;
     P->off_pacc = off;
     P->off_pstep = off;
     if (P->n_probes > 0) {
-        P->off_pcell = off;
-        off += align256(P->pcell_h.size() * sizeof(ProbeCell));
-        P->off_pstart = off;
-        off += align256((size_t)(P->n_probes + 1) * sizeof(int32_t));
+        P->off_pent = off;
+        off += align256(std::max<size_t>(1, P->pent_h.size()) * sizeof(ProbeEntry));
+        P->off_ptile = off;
+        off += align256(P->ptile_h.size() * sizeof(int32_t));
         P->off_pmom = off;
         off += align256((size_t)P->M * 3 * sizeof(double));
         P->off_pacc = off;
         off += align256((size_t)P->n_windows * P->n_probes * 3 * sizeof(double));
         P->off_pstep = off;
-        off += align256((size_t)P->n_probes * sizeof(int32_t));
+        off += align256((size_t)3 * P->n_probes * sizeof(int32_t));
     }
     P->scratch_bytes = off;
 
@@ -359,6 +414,7 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     P->scale_h[0] = h2;
     for (int t = 0; t < P->n_tallies; ++t) P->scale_h[1 + t] = h2;
     for (int r = 0; r < 2 * P->n_rects; ++r) P->scale_h[1 + P->n_tallies + r] = P->h;
+    for (int m = 0; m < 3 * P->n_probes; ++m) P->scale_h[1 + P->n_tallies + 2 * P->n_rects + m] = 1.0;
     double sw = 0;
     for (int k = 0; k < P->M; ++k) sw += P->w[k];
     double sq = 0;
@@ -403,15 +459,22 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
         const double A = P->h * P->h, eps = A * A * A;  // K A^3 with K = 1 (Sec. 4.2)
         a.eps2 = (float)(eps * eps);
     }
+    a.n_probes = P->n_probes;
+    a.qprobe = 1 + P->n_tallies + 2 * P->n_rects;
+    if (P->n_probes > 0) {
+        a.pent = P->sp<ProbeEntry>(P->off_pent);
+        a.ptile = P->sp<int32_t>(P->off_ptile);
+        a.pmom = P->sp<double>(P->off_pmom);
+    }
     return a;
 }
 
 int snh::finalize_workgroups(const sn_plan* P, int kind) {
     const int phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
-    return P->nq + phi_wg + (kind < 0 ? 0 : P->n_probes);
+    return P->nq + phi_wg;
 }
 
-FinalizeArgs snh::finalize_args(const sn_plan* P, int kind, const char* psi_in) {
+FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     const int l = kind == 2 ? 1 : 0;  // layout of the stage just run
     FinalizeArgs f{};
     f.phi_part = P->sp<float>(P->off_phi_part);
@@ -434,18 +497,13 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind, const char* psi_in) 
     f.nq = P->nq;
     f.fluence = P->fluence ? P->sp<double>(P->off_fluence) : nullptr;
     f.n_probes = kind < 0 ? 0 : P->n_probes;
+    f.qprobe = 1 + P->n_tallies + 2 * P->n_rects;
     if (P->n_probes > 0) {
-        f.psi_in = psi_in;
-        f.pcell = P->sp<ProbeCell>(P->off_pcell);
-        f.pstart = P->sp<int32_t>(P->off_pstart);
-        f.pmom = P->sp<double>(P->off_pmom);
         f.pacc = P->sp<double>(P->off_pacc);
         f.pstep = P->sp<int32_t>(P->off_pstep);
         f.pcoef = f.coef / (P->t_end / P->n_windows);
         f.n_windows = P->n_windows;
         f.nt = P->nt;
-        f.M = P->M;
-        f.dtype = P->dtype;
         f.last_stage = kind == 0 || kind == 2 ? 1 : 0;
     }
     return f;
@@ -511,7 +569,7 @@ sn_status launch_stage_pair(sn_plan* P, int kind, hipStream_t s, bool allow_timi
         P->ev_kind[P->ev_used] = kind;
         P->ev_used++;
     }
-    const FinalizeArgs f = finalize_args(P, kind, in);
+    const FinalizeArgs f = finalize_args(P, kind);
     HIP_TRY(launch_finalize(f, s), "finalize launch");
     return SN_OK;
 }
@@ -696,24 +754,17 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
         HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_fluence), 0, (size_t)P->nx * P->ny * sizeof(double), s),
                 "clear fluence");
     if (P->n_probes > 0) {
-        std::vector<ProbeCell> pc(P->pcell_h);
-        for (ProbeCell& c : pc) {
-            const int64_t j = c.off / P->nx, i = c.off - j * P->nx;
-            c.off = P->origin + j * P->pitch + i;
-        }
-        if (!pc.empty())
-            HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pcell), pc.data(), pc.size() * sizeof(ProbeCell),
-                                   hipMemcpyHostToDevice, s), "upload probe cells");
-        HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pstart), P->pstart_h.data(), P->pstart_h.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, s), "upload probe starts");
+        if (!P->pent_h.empty())
+            HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pent), P->pent_h.data(), P->pent_h.size() * sizeof(ProbeEntry),
+                                   hipMemcpyHostToDevice, s), "upload probe entries");
+        HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_ptile), P->ptile_h.data(), P->ptile_h.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s), "upload probe tiles");
         HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pmom), P->pmom_h.data(), P->pmom_h.size() * sizeof(double),
                                hipMemcpyHostToDevice, s), "upload probe moments");
         HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_pacc), 0,
                                (size_t)P->n_windows * P->n_probes * 3 * sizeof(double), s), "clear probe windows");
-        HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_pstep), 0, (size_t)P->n_probes * sizeof(int32_t), s),
+        HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_pstep), 0, (size_t)3 * P->n_probes * sizeof(int32_t), s),
                 "clear probe steps");
-        // the host copy above must outlive the asynchronous upload
-        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     }
     HIP_TRY(hipMemsetAsync(P->psi[0], 0, P->psi_bytes, s), "clear psi A");
     HIP_TRY(hipMemsetAsync(P->psi[1], 0, P->psi_bytes, s), "clear psi B");

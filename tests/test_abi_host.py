@@ -139,3 +139,55 @@ def test_calls_in_wrong_order_fail_cleanly(L):
         assert lib.sn_plan_use_graph(h, 3) == L.SN_ERR_INVALID
     finally:
         lib.sn_plan_destroy(h)
+
+
+def _create_probes(L, p, probes):
+    m = L.MarshalledProblem(p, probes=probes)
+    h = ctypes.c_void_p()
+    st = L.lib().sn_plan_create(ctypes.byref(m.struct), ctypes.byref(h))
+    if st == 0:
+        L.lib().sn_plan_destroy(h)
+    return st, L.lib().sn_last_error().decode()
+
+
+def test_probe_statements(L):
+    """Probe lists are validated on the host; a tile of 128 x 8 cells (the
+    default launch shape) takes at most 64 loader lanes of 8 cells, a lane's
+    cells all of one probe."""
+    from paper_2505_17284_amd import hohlraum
+
+    p = I.hohlraum(260, 32)
+    pr = hohlraum.probe_cells(p)
+    assert _create_probes(L, p, pr)[0] == 0
+    bad = dict(pr, n_probes=L.MAX_PROBES + 1)
+    st, msg = _create_probes(L, p, bad)
+    assert st == L.SN_ERR_INVALID and "n_probes" in msg, msg
+    cells = pr["cells"].copy()
+    cells["probe"][0] = 4
+    st, msg = _create_probes(L, p, dict(pr, cells=cells))
+    assert st == L.SN_ERR_INVALID and "probe 4" in msg, msg
+    cells = pr["cells"].copy()
+    cells["cell"][0] = 260 * 260
+    st, msg = _create_probes(L, p, dict(pr, cells=cells))
+    assert st == L.SN_ERR_INVALID and "cell index" in msg, msg
+
+    # capacity of one tile: columns 0..127, rows 0..7
+    def tile_cells(counts):
+        recs, c = [], 0
+        for q, n in enumerate(counts):
+            for _ in range(n):
+                recs.append(((c // 128) * 260 + c % 128, q, 1.0 / n))
+                c += 1
+        return dict(n_probes=len(counts), n_windows=3, cells=np.array(recs, dtype=L.PROBE_CELL))
+
+    assert _create_probes(L, p, tile_cells([512]))[0] == 0          # 64 lanes of 8
+    # 505 cells need 64 lanes of 8 (one slot free); the other probe needs a lane of its own
+    st, msg = _create_probes(L, p, tile_cells([505, 7]))
+    assert st == L.SN_ERR_UNSUPPORTED and "probe cells in the tile" in msg, msg
+    st, msg = _create_probes(L, p, tile_cells([513]))
+    assert st == L.SN_ERR_UNSUPPORTED, msg
+    assert _create_probes(L, p, tile_cells([448] + [8] * 7))[0] == 0  # 56 + 7 lanes
+    # a ball of radius 30 h fits wherever it sits
+    q = I.hohlraum(1300, 32)
+    big = hohlraum.probe_cells(q, centres=((0.0, 0.0), (0.3, -0.2)), r=30 * q.h)
+    assert _create_probes(L, q, big)[0] == 0

@@ -1,9 +1,10 @@
 """Space-time probes (Hohlraum QoI-1, Sec. 3.2.1) on the GPU, through the C
 ABI, against the FP64 oracle.
 
-Each probe block of the finalize reduces phi, J_x and J_y of the stage input
-over the probe's weighted cells into the window of the current step, with the
-stage's time weight. Against the oracle the window averages agree to 1e-5 of
+The stage kernels' loader wave sums phi, J_x and J_y of the stage input over
+each tile's weighted probe cells, read from the rows it stages in LDS; the
+finalize adds the totals, with the stage's time weight, to the window of the
+current step. Against the oracle the window averages agree to 1e-5 of
 the probe's phi scale (J_x and J_y are bounded by phi); across batch
 membership (Euler's alternating buffers included) and graph replay they are
 bit-identical.
@@ -138,3 +139,21 @@ def test_hohlraum260_full_run_probes_match_golden(sv):
     finally:
         plan.close()
     _compare(g, np.array(gold["probes"]), rtol=1e-4)
+
+
+@pytest.mark.parametrize("order,stepper,dtype,shape,rh", [
+    (2, I.HEUN, "f32", None, 12),
+    (1, I.EULER, "bf16", (4, 8), 8),
+    (3, I.HEUN, "f32", (4, 4), 8),
+])
+def test_eight_large_probes(sv, orc, order, stepper, dtype, shape, rh):
+    """Eight probes of radius 12 h (about 450 cells each, over several 128 x 8
+    tiles, several cells per loader lane) or, with the taller 128 x 32 and
+    128 x 16 tiles, 8 h (two probes sharing a tile), two of them clipped by
+    the domain, on a random state of the Hohlraum at n = 260: 6 steps in 4
+    windows."""
+    p = I.hohlraum(260, 32, order=order, stepper=stepper, psi_dtype=dtype, t_end=0.015)
+    geom = dict(centres=((-0.5, -0.5), (-0.2, 0.1), (0.1, 0.3), (0.4, -0.3), (0.55, 0.55), (-0.62, 0.6),
+                         (0.0, 0.0), (0.3, 0.62)), r=rh * p.h, n_windows=4)
+    kw = {} if shape is None else dict(rows_per_wave=shape[0], waves_per_group=shape[1])
+    _run(sv, orc, p, geom, psi0=I.random_state(p, 5), rtol=1e-2 if dtype == "bf16" else 1e-5, **kw)
