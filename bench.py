@@ -93,9 +93,19 @@ def cpu_baseline(problem, budget_s=15.0):
     psi, _ = oracle.advance(problem, psi, steps)
     secs = time.perf_counter() - t0
     ups = problem.cell_ordinates * steps / secs
+    # the same on one thread: one whole step
+    oracle.threads(1)
+    try:
+        t0 = time.perf_counter()
+        psi, _ = oracle.advance(problem, psi, 1)
+        secs1 = time.perf_counter() - t0
+    finally:
+        oracle.threads(threads)
     return {"value": ups, "unit": "cell-ordinate updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} Heun steps of the {problem.nx}x{problem.ny}x{problem.M} lattice "
-                      f"(FP64, {threads} OpenMP threads, {secs:.1f} s)"}
+                      f"(FP64, {threads} OpenMP threads, {secs:.1f} s)",
+            "value_1_thread": problem.cell_ordinates / secs1,
+            "sample_1_thread": f"1 Heun step of the same lattice on one thread ({secs1:.1f} s)"}
 
 
 def time_workload(p, workload, steps, warmup=3):
@@ -191,6 +201,21 @@ def time_venkat(steps, dtype, warmup=2):
     return time_workload(p, "lattice700_M256_heun_venkat", steps, warmup)
 
 
+def time_shard(steps, dtype, shards=8, warmup=3):
+    """One GPU's share of the full-size cavity split by ordinates over
+    `shards` GPUs: 1300^2 cells with 512 / shards ordinates (a product
+    quadrature of that size, which costs the same as a subset of the 512).
+    Each stage of a split solve ends with an all-reduce of the nx ny FP32
+    scalar-flux partial; its size is reported beside the stage times."""
+    from paper_2505_17284_amd import inputs as I
+
+    M = 512 // shards
+    p = I.cavity(1300, M, psi_dtype=dtype, name=f"cavity1300_M{M}")
+    out = time_workload(p, f"cavity1300_M{M}_heun2 (1/{shards} of 512 ordinates)", steps, warmup)
+    out["phi_allreduce_bytes_per_stage"] = p.nx * p.ny * 4
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +244,9 @@ def main():
     ap.add_argument("--hohlraum-steps", type=int, default=20,
                     help="Heun steps timed on the 1300^2 x 256 Hohlraum with and without its probes and "
                          "fluence (0 skips it)")
+    ap.add_argument("--shard-steps", type=int, default=40,
+                    help="Heun steps timed on one GPU's share of an 8-way ordinate split of the cavity, "
+                         "1300^2 x 64 ordinates (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -313,6 +341,8 @@ def main():
         line["venkat"] = time_venkat(args.venkat_steps, args.dtype)
     if args.hohlraum_steps:
         line["hohlraum"] = time_hohlraum(args.hohlraum_steps, args.dtype)
+    if args.shard_steps:
+        line["shard_share"] = time_shard(args.shard_steps, args.dtype)
     from paper_2505_17284_amd import serve
 
     if args.uq:

@@ -197,8 +197,18 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
     *waves = 4;
     const int wg_rows = *waves * *rows;
     const long tiles = (long)((P->nx + kTileX - 1) / kTileX) * ((P->ny + wg_rows - 1) / wg_rows);
+    // Groups of at least 8 ordinates; at least 8 groups (one per XCD) unless
+    // the launch already holds 4 K workgroups and that would leave fewer
+    // than 16 ordinates per group: the 1300 x 1300 cavity with 64 ordinates
+    // (one GPU's share of an 8-way ordinate split of 512) takes 0.52 ms per
+    // step with 4 groups of 16 against 0.62 ms with 8 groups of 8.
     int g = 1;
-    while ((tiles * g < 4096 || g < 8) && (P->M + 2 * g - 1) / (2 * g) >= 8) g *= 2;
+    for (;;) {
+        const int next = (P->M + 2 * g - 1) / (2 * g);  // ordinates per group after doubling
+        if (next < 8) break;
+        if (tiles * g < 4096 || (g < 8 && next >= 16)) g *= 2;
+        else break;
+    }
     *group_size = (P->M + g - 1) / g;
     // With FP32 storage, groups of more than 32 ordinates measured slower on
     // large M: 700 x 700 with 1936 ordinates, stage 1 1.83 ms with 32 per
