@@ -201,6 +201,34 @@ def time_venkat(steps, dtype, warmup=2):
     return time_workload(p, "lattice700_M256_heun_venkat", steps, warmup)
 
 
+def stream_ceiling(mib, reps=5):
+    """What plain streaming kernels reach on this GPU: torch's elementwise
+    add (two reads, one write: the mix of Heun's averaging stage) and a
+    device copy (one read, one write: the update stage), mib MiB per array,
+    best of `reps` launches timed with events."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    out = {"bytes_per_array": n * 4}
+    for label, fn, arrays in (("add", lambda: torch.add(a, b, out=c), 3), ("copy", lambda: c.copy_(a), 2)):
+        fn()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[f"{label}_GBs"] = arrays * n * 4 / (best * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.synchronize()
+    return out
+
+
 def time_shard(steps, dtype, shards=8, warmup=3):
     """One GPU's share of the full-size cavity split by ordinates over
     `shards` GPUs: 1300^2 cells with 512 / shards ordinates (a product
@@ -247,6 +275,8 @@ def main():
     ap.add_argument("--shard-steps", type=int, default=40,
                     help="Heun steps timed on one GPU's share of an 8-way ordinate split of the cavity, "
                          "1300^2 x 64 ordinates (0 skips it)")
+    ap.add_argument("--stream-mib", type=int, default=1024,
+                    help="MiB per array of the streaming-ceiling measurement (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for HBM byte counters)")
@@ -324,6 +354,11 @@ def main():
         "roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / (step_bytes / problem.cell_ordinates),
     }
     plan.close()
+    if args.stream_mib:
+        ceil = stream_ceiling(args.stream_mib)
+        line["stream_ceiling"] = ceil
+        line["roofline"]["frac_of_stream_ceiling"] = achieved / ceil["add_GBs"]
+        line["stage1"]["frac_of_copy_ceiling"] = stage1_gbs / ceil["copy_GBs"]
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20)
         src = torch.ones(n, dtype=torch.uint8, device=dev)
