@@ -1022,7 +1022,14 @@ template <int ORDER, int MODE, typename T, int TY, int W>
 __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_kernel(const StageArgs a) {
     extern __shared__ double facc_all[];  // [2 n_rects][kWave W] per-thread FP64 face accumulators
     __shared__ StageLds<T, TY, W, MODE, kExtraHalo<ORDER>> lds;
-    stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, xcd_contiguous(blockIdx.x, gridDim.x), facc_all, lds);
+    // The averaging stage runs its logical workgroups in reverse: it reads
+    // psi^(1), which the update stage just wrote in forward order, so it
+    // starts on the part most likely still held by the 256 MB Infinity Cache,
+    // and it leaves psi^(n+1)'s first groups, which the next update stage
+    // reads first, written last (700^2 x 256 lattice, FP32: 0.609 -> 0.601
+    // ms per Heun step; 1300^2 x 512 cavity: 3.73 -> 3.69 ms).
+    const int l = xcd_contiguous(blockIdx.x, gridDim.x);
+    stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, MODE == kAverage ? (int)gridDim.x - 1 - l : l, facc_all, lds);
 }
 
 // The selected instance j holding item (first[j] <= item < first[j + 1]):
