@@ -62,6 +62,31 @@ def measured_traffic(dtype):
     return float(fields["traffic_bytes_per_launch"])
 
 
+# VALU issue peak without packed FP32 (which this build leaves off): one
+# wave64 instruction per SIMD every 4 cycles, i.e. 16 lanes per cycle on each
+# of the 1024 SIMDs (256 CUs x 4) at 2.4 GHz.
+VALU_PEAK_LANE_OPS = 1024 * 16 * 2.4e9
+
+
+def measured_valu():
+    """SQ_INSTS_VALU per launch of the order-3 stage kernels (stage 1, stage 2)
+    on the 700^2 x 256 lattice, FP32, from the committed counter summary, or
+    None when it is missing or was taken on other sources."""
+    path = os.path.join(PROFILES, "stage_venkat_lattice700_M256_f32.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "valu_insts_stage1",
+                                                                  "valu_insts_stage2"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != source_digest() or "valu_insts_stage2" not in fields:
+        return None
+    return float(fields["valu_insts_stage1"]), float(fields["valu_insts_stage2"])
+
+
 def algorithmic_bytes(problem, plan_info, kind):
     """Algorithmic HBM bytes of one stage launch over the whole grid.
 
@@ -198,7 +223,16 @@ def time_venkat(steps, dtype, warmup=2):
     from paper_2505_17284_amd import inputs as I
 
     p = I.config(2).replace(order=3, psi_dtype=dtype, name="lattice700_M256_venkat")
-    return time_workload(p, "lattice700_M256_heun_venkat", steps, warmup)
+    out = time_workload(p, "lattice700_M256_heun_venkat", steps, warmup)
+    valu = measured_valu() if dtype == "f32" else None
+    if valu is not None:
+        # bound by its arithmetic: VALU lane-instructions per second against the issue peak
+        achieved = valu[1] * 64 / (out["stage2_kernel_ms"] * 1e-3)
+        out["alu"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_LANE_OPS,
+                      "unit": "VALU lane-instructions/s (SQ_INSTS_VALU x 64 / kernel time)",
+                      "frac": achieved / VALU_PEAK_LANE_OPS, "kernel": "sn_stage_kernel<3, kAverage>",
+                      "stage1_frac": valu[0] * 64 / (out["stage1_kernel_ms"] * 1e-3) / VALU_PEAK_LANE_OPS}
+    return out
 
 
 def stream_ceiling(mib, reps=5):
