@@ -191,3 +191,24 @@ def test_probe_statements(L):
     q = I.hohlraum(1300, 32)
     big = hohlraum.probe_cells(q, centres=((0.0, 0.0), (0.3, -0.2)), r=30 * q.h)
     assert _create_probes(L, q, big)[0] == 0
+
+
+def test_default_launch_shapes(L):
+    """The default ordinate groups of the measured workloads (host only):
+    32 per group on the benchmark lattice with the averaging stage halved, 32
+    on the cavity (not halved: more than 2^20 cells), 16 for one GPU's
+    64-ordinate share of the cavity, 8 for small grids that need the
+    workgroups, and no halving with BF16 storage or the Venkatakrishnan
+    limiter."""
+    from paper_2505_17284_amd import solver
+
+    def g(p):
+        i = solver.plan_info(p)
+        return i["group_size"], i["group_size_average"], i["rows_per_wave"], i["waves_per_group"]
+
+    assert g(I.config(2)) == (32, 16, 2, 4)
+    assert g(I.config(2).replace(psi_dtype="bf16")) == (32, 32, 2, 4)
+    assert g(I.config(2).replace(order=3)) == (32, 32, 2, 4)
+    assert g(I.config(3)) == (32, 32, 2, 4)
+    assert g(I.cavity(1300, 64)) == (16, 16, 2, 4)
+    assert g(I.lattice(140, 64, order=2, stepper=I.HEUN)) == (8, 8, 2, 4)
