@@ -81,16 +81,29 @@ def arrival_quotas(order: list, costs: dict, k: int, backfill: float = 0.25, min
     return out
 
 
+def response_ratio_order(keys, wait_s: dict, rem_s: dict, tiebreak: dict) -> list:
+    """keys by highest response ratio first, (wait + remaining) / remaining
+    (both in seconds; ties by `tiebreak`, e.g. arrival order): a short request
+    outranks a long one that has waited as long, and a long one outranks short
+    ones once it has waited long enough relative to its own remaining time."""
+    return sorted(keys, key=lambda k: (-(wait_s[k] + rem_s[k]) / rem_s[k], tiebreak[k]))
+
+
 def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_run: int = 32,
           rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "srpt", verbose: bool = False,
-          batch_factory=None, max_steps_per_run: int = 256, run_work: float = 2e10):
+          batch_factory=None, max_steps_per_run: int = 256, run_work: float = 2e10, service_rate: float = 8e11):
     """Continuous batching over `requests` = [(arrival_s, Problem)], Heun + minmod.
 
     policy "srpt": the admitted request with the least remaining work (psi
     steps x bytes per step) takes full runs and the others fill in by the same
     rule, so short requests overtake long ones that are already running (the
     GPU is shared by preemption at run boundaries; each request still runs at
-    the full speed of its own kernels); "arrival": the same with the oldest
+    the full speed of its own kernels); "hrrn": the same with the highest
+    response ratio (time since arrival + remaining time) / remaining time
+    first, re-ranked every run, the remaining time estimated from the rate
+    measured so far (service_rate psi-step bytes per second until then):
+    short requests still overtake, but a long one's ratio grows while it
+    waits, which bounds its delay; "arrival": the same with the oldest
     request first, so no request is slowed much by later arrivals; "work": per-run step quotas share the GPU by work (short
     requests finish fast, long ones are slowed down); "steps": every admitted
     request takes steps_per_run steps per run. With "arrival" a run holds at
@@ -121,6 +134,7 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
     changed = False
     t0 = time.perf_counter()
     windows = 0
+    busy_s, work_done = 0.0, 0.0  # measured service rate (hrrn)
     try:
         while finished < len(requests):
             now = time.perf_counter() - t0
@@ -153,6 +167,14 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
                            for key, i in slot_of.items()}
                     order = sorted(slot_of, key=lambda key: (rem[key], slot_of[key]))
                     quotas = arrival_quotas(order, costs, steps_per_run, backfill=0.1, min_work=run_work, k_max=k_max)
+                elif policy == "hrrn":
+                    rate = work_done / busy_s if busy_s > 0 and work_done > 0 else service_rate
+                    now = time.perf_counter() - t0
+                    rem_s = {key: max(costs[key] * (n_steps[i] - batches[key[0]].status(key[1])[1]) / rate, 1e-6)
+                             for key, i in slot_of.items()}
+                    wait_s = {key: now - requests[i][0] for key, i in slot_of.items()}
+                    order = response_ratio_order(list(slot_of), wait_s, rem_s, slot_of)
+                    quotas = arrival_quotas(order, costs, steps_per_run, backfill=0.1, min_work=run_work, k_max=k_max)
                 else:
                     quotas = {key: steps_per_run for key in costs}
                 for (d, s), q in quotas.items():
@@ -163,11 +185,18 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
                 if nxt < len(requests):
                     time.sleep(max(0.0, requests[nxt][0] - (time.perf_counter() - t0)))
                 continue
+            if policy == "hrrn":
+                before = {key: batches[key[0]].status(key[1])[1] for key in slot_of}
+                tw = time.perf_counter()
             for b in active:
                 b.run()
             windows += 1
             for b in active:
                 b.synchronize()
+            if policy == "hrrn":
+                busy_s += time.perf_counter() - tw
+                work_done += sum(costs[key] * (batches[key[0]].status(key[1])[1] - st) for key, st in before.items())
+                changed = True  # ratios move with time: re-rank every run
             for d, b in batches.items():
                 for s in b.done_slots():
                     i = slot_of.pop((d, s))

@@ -197,3 +197,35 @@ def test_arrival_policy_never_throttles_the_oldest_request():
         assert n >= 8 or fin, "the oldest admitted request was throttled"
         paused += sum(1 for n, _ in live.values() if n == 0)
     assert b.runs
+
+
+def test_response_ratio_order():
+    keys = ["long", "short", "mid"]
+    rem = {"long": 10.0, "short": 0.5, "mid": 2.0}
+    tie = {"long": 0, "short": 1, "mid": 2}
+    # all fresh: ratios are 1, arrival order decides
+    assert serve.response_ratio_order(keys, {k: 0.0 for k in keys}, rem, tie) == ["long", "short", "mid"]
+    # equal waits: the shortest remaining time leads
+    assert serve.response_ratio_order(keys, {k: 1.0 for k in keys}, rem, tie) == ["short", "mid", "long"]
+    # a long request that has waited 10x its remaining time outranks a short one that waited 1x its own
+    assert serve.response_ratio_order(keys, {"long": 100.0, "short": 0.5, "mid": 1.0}, rem, tie)[0] == "long"
+
+
+def test_hrrn_policy_serves_everything_and_re_ranks_every_run():
+    MockBatch.made.clear()
+    big = I.lattice(80, 64, order=2, stepper=I.HEUN, name="big")
+    reqs = [(0.0, big)] + [(0.0, I.lattice(40, 32, order=2, stepper=I.HEUN, t_end=0.7, name=f"s{i}"))
+                           for i in range(6)]
+    rec, tot = serve.serve(reqs, 10 ** 12, max_instances=8, steps_per_run=4, max_steps_per_run=4, policy="hrrn",
+                           run_work=0.0, batch_factory=MockBatch)
+    assert all(r["done"] is not None for r in rec)
+    (b,) = MockBatch.made
+    # every run has a head taking its full quota (or finishing)
+    for took in b.runs:
+        assert any(n == 4 or fin for n, _, fin in took.values())
+    # equal waits: a short request leads the first run, and the short ones,
+    # whose ratios grow faster, finish first
+    first = {name: n for n, name, _ in b.runs[0].values()}
+    assert any(first[f"s{i}"] == 4 for i in range(6)) and first["big"] < 4
+    by = {r["name"]: r for r in rec}
+    assert max(by[f"s{i}"]["done"] for i in range(6)) < by["big"]["done"]
