@@ -320,3 +320,27 @@ def test_full_size_tessellation22_random_state(sv, orc):
     okp, repp = compare_field(g_["phi"], o_["phi"], 2)
     print("phi:", repp)
     assert okp, repp
+
+
+def test_full_size_cavity_share_of_eight(sv, orc):
+    """One GPU's share of an 8-way ordinate split of the full-size cavity:
+    1300^2 cells with 64 ordinates, in its default launch shape (4 groups of
+    16 ordinates). One Heun step from a smooth random state: every QoI,
+    sampled psi and all of phi against the oracle."""
+    p = I.cavity(1300, 64)
+    info = sv.plan_info(p)
+    assert (info["group_size"], info["group_size_average"]) == (16, 16)
+    psi0 = I.random_state(p, 77, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 1, psi0=psi0)
+    oi, oint = _orc_dicts(o_)
+    ok, rep = compare_qoi(g_["qoi"], g_["qoi_int"], oi, oint)
+    print(rep)
+    assert ok, rep
+    rng = np.random.Generator(np.random.PCG64(8))
+    idx = tuple(rng.integers(0, s, 20000) for s in o_["psi"].shape)
+    okf, repf = compare_field(g_["psi"][idx], o_["psi"][idx], 2)
+    print("sampled psi:", repf)
+    assert okf, repf
+    okp, repp = compare_field(g_["phi"], o_["phi"], 2)
+    print("phi:", repp)
+    assert okp, repp
