@@ -416,7 +416,7 @@ def main():
 
     if args.uq:
         print(f"[bench] batched UQ: {args.uq} lattice draws", file=sys.stderr, flush=True)
-        line["batched_uq"] = serve.uq(args.uq, verbose=True)
+        line["batched_uq"] = serve.uq(args.uq, verbose=True, tune=True, compare_default=True)
     if args.serving_requests:
         print(f"[bench] serving: {args.serving_requests} requests at load {args.serving_load}",
               file=sys.stderr, flush=True)

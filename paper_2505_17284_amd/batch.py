@@ -33,9 +33,10 @@ class Busy(RuntimeError):
 
 
 def footprint(problem, rows_per_wave: int = 0, waves_per_group: int = 0, group_size: int = 0,
-              fluence: bool = False, probes=None) -> int:
+              fluence: bool = False, probes=None, group_size_average: int = 0) -> int:
     """HBM bytes a problem occupies while admitted (two psi buffers + scratch); host only."""
-    info = solver.plan_info(problem, group_size, rows_per_wave, waves_per_group, fluence=fluence, probes=probes)
+    info = solver.plan_info(problem, group_size, rows_per_wave, waves_per_group, group_size_average,
+                            fluence=fluence, probes=probes)
     return 2 * int(info["psi_bytes"]) + int(info["scratch_bytes"])
 
 
@@ -69,28 +70,34 @@ class Batch:
         torch = solver._torch()
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def footprint(self, problem, group_size: int = 0, fluence: bool = False, probes=None) -> int:
-        return footprint(problem, self.opts.rows_per_wave, self.opts.waves_per_group, group_size, fluence, probes)
+    def footprint(self, problem, group_size: int = 0, fluence: bool = False, probes=None,
+                  group_size_average: int = 0) -> int:
+        return footprint(problem, self.opts.rows_per_wave, self.opts.waves_per_group, group_size, fluence, probes,
+                         group_size_average)
 
-    def fits(self, problem, group_size: int = 0, fluence: bool = False, probes=None) -> bool:
+    def fits(self, problem, group_size: int = 0, fluence: bool = False, probes=None,
+             group_size_average: int = 0) -> bool:
         if len(self.plans) >= self.opts.max_instances:
             return False
         if not self.opts.hbm_budget_bytes:
             return True
-        return (self.bytes_admitted + self.footprint(problem, group_size, fluence, probes)
+        return (self.bytes_admitted + self.footprint(problem, group_size, fluence, probes, group_size_average)
                 <= self.opts.hbm_budget_bytes)
 
-    def admit(self, problem, psi0=None, group_size: int = 0, fluence: bool = False, probes=None) -> int:
+    def admit(self, problem, psi0=None, group_size: int = 0, fluence: bool = False, probes=None,
+              group_size_average: int = 0) -> int:
         """Allocate, initialise and admit one problem; returns its slot. Raises Busy.
         With ``fluence`` / ``probes`` the slot's plan also accumulates the time
-        integral of phi / the probes' window averages (``plan(slot)``)."""
+        integral of phi / the probes' window averages (``plan(slot)``).
+        group_size / group_size_average: ordinates per workgroup of the update
+        and averaging stages (0: the defaults; group_size alone sets both)."""
         if problem.psi_dtype != self.psi_dtype:
             raise ValueError(f"problem stores psi as {problem.psi_dtype}, the batch as {self.psi_dtype}")
-        if not self.fits(problem, group_size, fluence, probes):
+        if not self.fits(problem, group_size, fluence, probes, group_size_average):
             raise Busy(f"{problem.name}: no slot or budget free")
         plan = solver.Plan(problem, group_size=group_size, rows_per_wave=self.opts.rows_per_wave,
                            waves_per_group=self.opts.waves_per_group, device=str(self.device), psi0=psi0,
-                           fluence=fluence, probes=probes)
+                           fluence=fluence, probes=probes, group_size_average=group_size_average)
         slot = ctypes.c_int32(-1)
         st = lib().sn_batch_admit(self.h, plan.h, ctypes.byref(slot))
         if st == SN_ERR_BUSY:

@@ -275,9 +275,23 @@ def same_results(rec_a, rec_b, rtol: float = 1e-5):
 
 
 def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_alone: bool = True,
-       psi_dtype: str = "f32", verbose: bool = False):
-    """The batched UQ workload: DP-2 lattice draws, all admitted at once, run to T."""
+       psi_dtype: str = "f32", verbose: bool = False, tune: bool = False, compare_default: bool = False):
+    """The batched UQ workload: DP-2 lattice draws, all admitted at once, run to T.
+    tune: admit every draw with the ordinate groups `solver.autotune` measures
+    for its (grid, ordinates) class (tuning time reported apart, not in
+    wall_s); the one-at-a-time comparison then uses the same groups, so that
+    speedup_vs_alone is the batching's alone. compare_default: also run the
+    batch with the library's default groups (speedup_vs_default_shapes)."""
     probs = [I.uq_instance(seed0 + s, psi_dtype=psi_dtype) for s in range(n_instances)]
+    shapes = [dict() for _ in probs]
+    tune_s = 0.0
+    if tune:
+        t0 = time.perf_counter()
+        for p, sh in zip(probs, shapes):
+            t = solver.autotune(p)
+            sh.update(group_size=t["group_size"], group_size_average=t["group_size_average"])
+        _sync()
+        tune_s = time.perf_counter() - t0
     work = 0
     for p in probs:
         nt = solver.plan_info(p)["n_steps"]
@@ -287,7 +301,7 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
     b = B.Batch(order=2, stepper=I.HEUN, psi_dtype=psi_dtype, max_instances=n_instances,
                 steps_per_run=steps_per_run)
     try:
-        slots = [b.admit(p) for p in probs]
+        slots = [b.admit(p, **sh) for p, sh in zip(probs, shapes)]
         t_admit = time.perf_counter() - t0
         while b.unfinished():
             b.run()
@@ -298,13 +312,18 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
         peak = info["bytes_admitted"]
     finally:
         b.close()
-    out = dict(instances=n_instances, wall_s=secs, admit_s=t_admit, solves_per_s=n_instances / secs,
+    out = dict(instances=n_instances, tuned=tune, tune_s=tune_s, wall_s=secs, admit_s=t_admit,
+               solves_per_s=n_instances / secs,
                updates_per_s=work / secs, cell_ord_steps=work, peak_bytes=peak,
                graph_replays=info["graph_replays"], launches=info["launches"])
+    if compare_default and tune:
+        d = uq(n_instances, seed0, steps_per_run, compare_alone=False, psi_dtype=psi_dtype, tune=False)
+        out["default_shapes_wall_s"] = d["wall_s"]
+        out["speedup_vs_default_shapes"] = d["wall_s"] / secs
     if compare_alone:
         _sync()
         t0 = time.perf_counter()
-        alone = [solver.solve(p) for p in probs]
+        alone = [solver.solve(p, **sh) for p, sh in zip(probs, shapes)]
         _sync()
         secs_a = time.perf_counter() - t0
         out["alone_wall_s"] = secs_a

@@ -205,4 +205,50 @@ def solve(problem, steps: int | None = None, psi0=None, return_psi: bool = False
         plan.close()
 
 
-__all__ = ["Plan", "solve", "plan_info", "qoi_dicts", "SnError"]
+_TUNED: dict = {}
+
+# (update stage, averaging stage) ordinates per group tried by autotune; 0
+# is the library's default for the shape.
+TUNE_CANDIDATES = ((0, 0), (8, 8), (16, 16), (32, 16), (32, 32), (64, 32), (64, 64))
+
+
+def autotune(problem, candidates=TUNE_CANDIDATES, steps: int = 4, reps: int = 2, device: str = "cuda:0") -> dict:
+    """The fastest ordinate-group sizes for the problem's shape class (grid,
+    ordinates, order, stepper, storage), measured on the device: for every
+    distinct effective candidate, the best of `reps` wall-clock timings of
+    `steps` whole steps (stages, finalizes, launches) after one warm-up step.
+    Cached per class for the life of the process; returns group_size,
+    group_size_average and the measured ms per step."""
+    import time
+
+    torch = _torch()
+    key = (problem.nx, problem.ny, problem.M, problem.order, problem.stepper, problem.psi_dtype)
+    if key in _TUNED:
+        return _TUNED[key]
+    best = None
+    seen = set()
+    for gs, gsa in candidates:
+        info = plan_info(problem, group_size=gs, group_size_average=gsa or gs)
+        eff = (info["group_size"], info["group_size_average"])
+        if eff in seen:
+            continue
+        seen.add(eff)
+        plan = Plan(problem, group_size=eff[0], group_size_average=eff[1], device=device)
+        try:
+            plan.run(1, unbounded=True)
+            t = float("inf")
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan.run(steps, unbounded=True)
+                torch.cuda.synchronize()
+                t = min(t, (time.perf_counter() - t0) * 1e3 / steps)
+        finally:
+            plan.close()
+        if best is None or t < best[0]:
+            best = (t, eff)
+    _TUNED[key] = dict(group_size=best[1][0], group_size_average=best[1][1], ms_per_step=best[0])
+    return _TUNED[key]
+
+
+__all__ = ["Plan", "solve", "plan_info", "qoi_dicts", "SnError", "autotune"]

@@ -245,3 +245,37 @@ def test_mismatched_plan_rejected(bt):
             b.admit(I.lattice(70, 32, order=1, stepper=I.EULER))
     finally:
         b.close()
+
+
+def test_autotuned_groups_in_a_batch(bt, orc):
+    """solver.autotune picks one of its candidates (cached per shape class);
+    a batch admitting plans with the tuned groups gives the same results as
+    the plans alone with those groups, and agrees with the oracle."""
+    batch, solver = bt
+    probs = [I.uq_instance(s).replace(t_end=0.1) for s in (0, 1, 2)]
+    tuned = []
+    for p in probs:
+        print(f"[case] autotune {p.name} n={p.nx} M={p.M}", flush=True)
+        t = solver.autotune(p)
+        assert t is solver.autotune(p)  # cached
+        info = solver.plan_info(p, group_size=t["group_size"], group_size_average=t["group_size_average"])
+        assert (info["group_size"], info["group_size_average"]) == (t["group_size"], t["group_size_average"])
+        assert t["ms_per_step"] > 0
+        tuned.append(dict(group_size=t["group_size"], group_size_average=t["group_size_average"]))
+    alone = [solver.solve(p, return_psi=True, rows_per_wave=2, waves_per_group=4, **sh) for p, sh in zip(probs, tuned)]
+    b = batch.Batch(order=2, stepper=I.HEUN, max_instances=4, steps_per_run=5)
+    try:
+        slots = [b.admit(p, **sh) for p, sh in zip(probs, tuned)]
+        while b.unfinished():
+            b.run()
+        for p, s, a in zip(probs, slots, alone):
+            _same(b.result(s, psi=True), a, p.name)
+    finally:
+        b.close()
+    for p, a in zip(probs, alone):
+        o = orc.solve(p)
+        from tests.test_gpu_parity import _orc_dicts
+
+        oi, oint = _orc_dicts(o)
+        ok, rep = compare_qoi(a["qoi"], a["qoi_int"], oi, oint)
+        assert ok, rep
