@@ -188,34 +188,40 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
     // Two rows per wave keep the staged windows, the per-cell constants and the
     // reconstructions within ~80 VGPRs. Four waves per workgroup: taller
     // workgroups stage fewer halo rows but measured slower on the 700 x 700
-    // lattice. Ordinate groups: at least 8 (one per XCD, so that the tiles an
-    // XCD holds at a time are neighbours that share their halo lines in its
-    // L2), and more until the launch holds ~4 K workgroups (16 per CU),
-    // keeping at least 8 ordinates per group so the per-workgroup set-up and
-    // the group's phi partial stay small.
+    // lattice. Ordinate groups as below; at least 8 ordinates per group keep
+    // the per-workgroup set-up and the group's phi partial small.
     *rows = 2;
     *waves = 4;
     const int wg_rows = *waves * *rows;
     const long tiles = (long)((P->nx + kTileX - 1) / kTileX) * ((P->ny + wg_rows - 1) / wg_rows);
-    // Groups of at least 8 ordinates; at least 8 groups (one per XCD) unless
-    // the launch already holds 4 K workgroups and that would leave fewer
-    // than 16 ordinates per group: the 1300 x 1300 cavity with 64 ordinates
-    // (one GPU's share of an 8-way ordinate split of 512) takes 0.52 ms per
-    // step with 4 groups of 16 against 0.62 ms with 8 groups of 8.
-    int g = 1;
-    for (;;) {
-        const int next = (P->M + 2 * g - 1) / (2 * g);  // ordinates per group after doubling
-        if (next < 8) break;
-        if (tiles * g < 4096 || (g < 8 && next >= 16)) g *= 2;
-        else break;
+    if (P->dtype == SN_F32) {
+        // 32 ordinates per group, halved (down to 8) while the launch would
+        // hold fewer than 400 workgroups. Timed over the lattice at grid sides
+        // 200 to 1000 with 64 to 512 ordinates, 32 per group is the fastest
+        // or within 5% everywhere but the smallest launches (200^2 x 64: 8
+        // per group, 2x faster; 200^2 x 128 and 300^2 x 64: 16), while aiming
+        // at 4 K workgroups had split mid-size grids into groups of 8 (500^2 x
+        // 256: 0.42 vs 0.31 ms per step). More than 32 per group is slower on
+        // large M (700 x 700 with 1936 ordinates, stage 1: 1.83 ms with 32
+        // per group, 2.27 ms with 242).
+        int gs = std::min(P->M, 32);
+        while (gs > 8 && tiles * ((P->M + gs - 1) / gs) < 400) gs = (gs + 1) / 2;
+        *group_size = gs;
+    } else {
+        // BF16 storage: groups of at least 8 ordinates and at least 8 groups
+        // (one per XCD) unless the launch already holds 4 K workgroups and
+        // that would leave fewer than 16 per group; more groups until it
+        // does. Large groups are faster here (1.74 vs 1.85 ms with 242 vs 32
+        // per group on the 1936-ordinate lattice), so there is no cap.
+        int g = 1;
+        for (;;) {
+            const int next = (P->M + 2 * g - 1) / (2 * g);  // ordinates per group after doubling
+            if (next < 8) break;
+            if (tiles * g < 4096 || (g < 8 && next >= 16)) g *= 2;
+            else break;
+        }
+        *group_size = (P->M + g - 1) / g;
     }
-    *group_size = (P->M + g - 1) / g;
-    // With FP32 storage, groups of more than 32 ordinates measured slower on
-    // large M: 700 x 700 with 1936 ordinates, stage 1 1.83 ms with 32 per
-    // group vs 2.27 ms with 242; the 1300 x 1300 x 512 cavity is level (1.61
-    // vs 1.65 ms with 64). With BF16 storage large groups are faster (1.74 vs
-    // 1.85 ms with 242 vs 32 on the 1936-ordinate lattice), so no cap there.
-    if (P->dtype == SN_F32) *group_size = std::min(*group_size, 32);
     // Heun's averaging stage also streams psi^n; with FP32 storage its LDS
     // slots are twice those of the update stage, and twice the groups (half
     // the ordinates each, while that leaves at least 16) measured faster on
@@ -226,7 +232,11 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
     // storage the halving measured slower (368 vs 330 us on the lattice), and
     // with the Venkatakrishnan limiter (order 3), whose stage is bound by its
     // arithmetic rather than by the copies in flight, too (572 vs 533 us).
-    const bool halve = *group_size >= 32 && P->dtype == SN_F32 && P->order < 3 &&
+    // Re-timed with the reversed averaging stage, the halving is worth little
+    // any more: 1-3.5% slower than whole groups at 256 and 512 ordinates on
+    // grids from 400^2 to 1000^2 (the benchmark lattice: level), 2-10% slower
+    // at 64 and 128; it is kept only at 256 ordinates and more.
+    const bool halve = *group_size >= 32 && P->dtype == SN_F32 && P->order < 3 && P->M >= 256 &&
                        (int64_t)P->nx * P->ny <= (1 << 20);
     *group_size_avg = halve ? (*group_size + 1) / 2 : *group_size;
 }

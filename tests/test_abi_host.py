@@ -196,10 +196,10 @@ def test_probe_statements(L):
 def test_default_launch_shapes(L):
     """The default ordinate groups of the measured workloads (host only):
     32 per group on the benchmark lattice with the averaging stage halved, 32
-    on the cavity (not halved: more than 2^20 cells), 16 for one GPU's
-    64-ordinate share of the cavity, 8 for small grids that need the
-    workgroups, and no halving with BF16 storage or the Venkatakrishnan
-    limiter."""
+    on the cavity (not halved: more than 2^20 cells) and on one GPU's
+    64-ordinate share of it, fewer on grids too small to fill the GPU
+    otherwise, and no halving with BF16 storage, the Venkatakrishnan limiter
+    or fewer than 256 ordinates."""
     from paper_2505_17284_amd import solver
 
     def g(p):
@@ -210,5 +210,8 @@ def test_default_launch_shapes(L):
     assert g(I.config(2).replace(psi_dtype="bf16")) == (32, 32, 2, 4)
     assert g(I.config(2).replace(order=3)) == (32, 32, 2, 4)
     assert g(I.config(3)) == (32, 32, 2, 4)
-    assert g(I.cavity(1300, 64)) == (16, 16, 2, 4)
+    assert g(I.cavity(1300, 64)) == (32, 32, 2, 4)
     assert g(I.lattice(140, 64, order=2, stepper=I.HEUN)) == (8, 8, 2, 4)
+    assert g(I.lattice(140, 256, order=2, stepper=I.HEUN)) == (16, 16, 2, 4)
+    assert g(I.lattice(560, 128, order=2, stepper=I.HEUN)) == (32, 32, 2, 4)
+    assert g(I.lattice(560, 256, order=2, stepper=I.HEUN)) == (32, 16, 2, 4)

@@ -324,12 +324,12 @@ def test_full_size_tessellation22_random_state(sv, orc):
 
 def test_full_size_cavity_share_of_eight(sv, orc):
     """One GPU's share of an 8-way ordinate split of the full-size cavity:
-    1300^2 cells with 64 ordinates, in its default launch shape (4 groups of
-    16 ordinates). One Heun step from a smooth random state: every QoI,
+    1300^2 cells with 64 ordinates, in its default launch shape (2 groups of
+    32 ordinates). One Heun step from a smooth random state: every QoI,
     sampled psi and all of phi against the oracle."""
     p = I.cavity(1300, 64)
     info = sv.plan_info(p)
-    assert (info["group_size"], info["group_size_average"]) == (16, 16)
+    assert (info["group_size"], info["group_size_average"]) == (32, 32)
     psi0 = I.random_state(p, 77, "smooth")
     g_, o_ = _run_both(sv, orc, p, 1, psi0=psi0)
     oi, oint = _orc_dicts(o_)
