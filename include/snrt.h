@@ -349,7 +349,7 @@ typedef struct sn_batch_opts {
                                     * take their stages as launches of their
                                     * own (kernel arguments, no instance
                                     * lookup); smaller plans share the batched
-                                    * launch. 0 = 4 per compute unit, -1 = never */
+                                    * launch. 0 = 2 per compute unit, -1 = never */
 } sn_batch_opts;
 
 typedef struct sn_batch_info {

@@ -265,14 +265,16 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
         if (!big.empty()) groups.push_back(big);
     }
     if (groups.empty()) return SN_OK;
-    // Members with at least this many workgroups per stage take their steps
+    // Members with at least this many workgroups per stage (default 2 per
+    // CU: with 4 per CU the serving mix ran 7% slower batched than one at a
+    // time, its mid-size plans going through the shared launch) take their steps
     // as launches of their own (plain kernel arguments, no instance lookup at
     // the start of every workgroup), all steps of the run of one member back
     // to back, after the shared launches: they fill the GPU by themselves,
     // and consecutive stages of one plan reuse what the cache holds of it.
     const int64_t direct_min = B->o.direct_min_workgroups < 0
                                    ? INT64_MAX
-                                   : (B->o.direct_min_workgroups > 0 ? B->o.direct_min_workgroups : 4 * (int64_t)B->cus);
+                                   : (B->o.direct_min_workgroups > 0 ? B->o.direct_min_workgroups : 2 * (int64_t)B->cus);
     struct Rec {
         size_t off;  // ints into the run area: sel [n], first [n+1], ffirst [n+1], fsel [n]
         int32_t n, total, ftotal, mode;

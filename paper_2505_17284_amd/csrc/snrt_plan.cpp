@@ -208,19 +208,16 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
         while (gs > 8 && tiles * ((P->M + gs - 1) / gs) < 400) gs = (gs + 1) / 2;
         *group_size = gs;
     } else {
-        // BF16 storage: groups of at least 8 ordinates and at least 8 groups
-        // (one per XCD) unless the launch already holds 4 K workgroups and
-        // that would leave fewer than 16 per group; more groups until it
-        // does. Large groups are faster here (1.74 vs 1.85 ms with 242 vs 32
-        // per group on the 1936-ordinate lattice), so there is no cap.
-        int g = 1;
-        for (;;) {
-            const int next = (P->M + 2 * g - 1) / (2 * g);  // ordinates per group after doubling
-            if (next < 8) break;
-            if (tiles * g < 4096 || (g < 8 && next >= 16)) g *= 2;
-            else break;
-        }
-        *group_size = (P->M + g - 1) / g;
+        // BF16 storage favours larger groups: 64 ordinates per group (M / 8
+        // when that is more: 242 per group on the 1936-ordinate lattice, 1.74
+        // vs 1.85 ms with 32), halved (down to 8) while the launch would hold
+        // fewer than 700 workgroups. Timed over the same lattice classes, 64
+        // per group is the fastest or within a few percent from 500^2 up (the
+        // 700^2 x 256 lattice: 0.554 vs 0.577 ms per step with 32; the 1300^2
+        // x 256 Hohlraum: 1.48 vs 1.57 ms), the smaller grids want 8 to 32.
+        int gs = std::max(std::min(P->M, 64), (P->M + 7) / 8);
+        while (gs > 8 && tiles * ((P->M + gs - 1) / gs) < 700) gs = (gs + 1) / 2;
+        *group_size = gs;
     }
     // Heun's averaging stage also streams psi^n; with FP32 storage its LDS
     // slots are twice those of the update stage, and twice the groups (half

@@ -199,7 +199,7 @@ def test_default_launch_shapes(L):
     on the cavity (not halved: more than 2^20 cells) and on one GPU's
     64-ordinate share of it, fewer on grids too small to fill the GPU
     otherwise, and no halving with BF16 storage, the Venkatakrishnan limiter
-    or fewer than 256 ordinates."""
+    or fewer than 256 ordinates; BF16 storage takes groups of 64."""
     from paper_2505_17284_amd import solver
 
     def g(p):
@@ -207,7 +207,7 @@ def test_default_launch_shapes(L):
         return i["group_size"], i["group_size_average"], i["rows_per_wave"], i["waves_per_group"]
 
     assert g(I.config(2)) == (32, 16, 2, 4)
-    assert g(I.config(2).replace(psi_dtype="bf16")) == (32, 32, 2, 4)
+    assert g(I.config(2).replace(psi_dtype="bf16")) == (64, 64, 2, 4)
     assert g(I.config(2).replace(order=3)) == (32, 32, 2, 4)
     assert g(I.config(3)) == (32, 32, 2, 4)
     assert g(I.cavity(1300, 64)) == (32, 32, 2, 4)
