@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the explicit S_N transport step on one MI355X.
 
-Workload: the lattice benchmark on a 700 x 700 grid with 256 ordinates
-(8 Gauss-Legendre polar x 32 azimuths), minmod second order, Heun, CFL 0.5
-(640 steps to T = 3.2). One step = both Heun stages with their scalar-flux
-epilogues and QoI reductions over the whole grid. Inputs are synthetic (the
-problem statement itself) and resident in HBM before timing starts.
+Workload (the headline line): the walled cavity on a 1300 x 1300 grid with
+512 ordinates (8 Gauss-Legendre polar x 64 azimuths), minmod second order,
+Heun, CFL 0.5 (5200 steps to T = 2.6); each FP32 psi buffer holds 3.5 GB,
+far more than the 256 MB Infinity Cache. One step = both Heun stages with
+their scalar-flux epilogues and QoI reductions over the whole grid. Inputs
+are synthetic (the problem statement itself) and resident in HBM before
+timing starts.
 
 Prints one JSON line. `value` = cell-ordinate updates per second (one update
-= one (cell, ordinate) advanced one full time step). `roofline` describes the
-dominant kernel (Heun stage 2) against 8 TB/s; `cpu_baseline` times the FP64
-oracle on a bounded sample of the same workload on the host cores.
-`batched_uq` runs 256 lattice draws (grid side 140..560, 64..256 ordinates)
-as one batch and one at a time; `serving` feeds Poisson arrivals of mixed
-lattice / cavity requests to the continuous-batching loop and to the
-one-at-a-time path and reports p50/p99 latency and solves/s for both.
+= one (cell, ordinate) advanced one full time step), timed over exactly
+--steps steps with no per-launch instrumentation. `roofline` describes the
+dominant kernel (Heun stage 2) against 8 TB/s, its average duration taken
+with HIP events on the launch stream in a second, separately timed pass;
+`step_roofline` is the whole step's algorithmic bytes over ms_per_step.
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same
+workload on the host cores. Further keys time the 700^2 x 256 lattice, the
+paper's tessellation quadrature and limiter, the Hohlraum, one GPU's share of
+an ordinate split, the batched UQ workload and a compact serving sweep.
 """
 
 import argparse
@@ -45,10 +49,11 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(dtype):
-    """HBM bytes per launch of the Heun stage-2 kernel from the committed rocprofv3
-    counter summary, or None when the summary is missing or was taken on other sources."""
-    path = os.path.join(PROFILES, f"stage_heun2_lattice700_M256_{dtype}.md")
+def measured_traffic(workload, dtype):
+    """HBM bytes per launch of the Heun stage-2 kernel on `workload` from the
+    committed rocprofv3 counter summary, or None when the summary is missing
+    or was taken on other sources."""
+    path = os.path.join(PROFILES, f"stage_heun2_{workload}_{dtype}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -101,55 +106,76 @@ def algorithmic_bytes(problem, plan_info, kind):
     return cells * problem.M * per_co + cells * 9
 
 
-def cpu_baseline(problem, budget_s=15.0):
-    """Time the oracle (as it stands) on whole Heun steps of the workload."""
+def cpu_baseline(problem, budget_s=12.0, share_M=64):
+    """Time the oracle (as it stands) on whole Heun steps of the workload.
+
+    Every oracle call copies the state and allocates its work arrays, so the
+    rate comes from the difference of two calls (1 step, then 1 + s steps)
+    on the same state. The one-thread figure takes a share of the ordinates
+    (the cavity's grid with a share_M-ordinate product quadrature: the
+    oracle's cost per cell-ordinate does not depend on M)."""
     import numpy as np
 
     import oracle
+    from paper_2505_17284_amd import inputs as I
 
     oracle.build(force=False)
     threads = oracle.threads(0)
-    psi = np.zeros((problem.M, problem.ny, problem.nx))
-    t0 = time.perf_counter()
-    psi, _ = oracle.advance(problem, psi, 1)
-    one = time.perf_counter() - t0
-    steps = max(1, min(50, int(budget_s / max(one, 1e-6))))
-    t0 = time.perf_counter()
-    psi, _ = oracle.advance(problem, psi, steps)
-    secs = time.perf_counter() - t0
-    ups = problem.cell_ordinates * steps / secs
-    # the same on one thread: one whole step
+
+    def rate(p, budget):
+        psi = np.zeros((p.M, p.ny, p.nx))
+        t0 = time.perf_counter()
+        psi, _ = oracle.advance(p, psi, 1)
+        one = time.perf_counter() - t0
+        steps = max(1, min(50, int(budget / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        psi1, _ = oracle.advance(p, psi, 1)
+        t1 = time.perf_counter() - t0
+        del psi1
+        t0 = time.perf_counter()
+        psi2, _ = oracle.advance(p, psi, 1 + steps)
+        t2 = time.perf_counter() - t0
+        del psi, psi2
+        return p.cell_ordinates * steps / max(t2 - t1, 1e-9), steps, t2 - t1
+
+    ups, steps, secs = rate(problem, budget_s)
+    share = problem.replace(quad=I.quadrature_for(share_M), name=f"{problem.name}_M{share_M}")
     oracle.threads(1)
     try:
-        t0 = time.perf_counter()
-        psi, _ = oracle.advance(problem, psi, 1)
-        secs1 = time.perf_counter() - t0
+        ups1, steps1, secs1 = rate(share, 4.0)
     finally:
         oracle.threads(threads)
     return {"value": ups, "unit": "cell-ordinate updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} Heun steps of the {problem.nx}x{problem.ny}x{problem.M} lattice "
-                      f"(FP64, {threads} OpenMP threads, {secs:.1f} s)",
-            "value_1_thread": problem.cell_ordinates / secs1,
-            "sample_1_thread": f"1 Heun step of the same lattice on one thread ({secs1:.1f} s)"}
+            "sample": f"{steps} Heun steps of the {problem.nx}x{problem.ny}x{problem.M} {problem.meta.get('kind', '')} "
+                      f"(FP64, {threads} OpenMP threads, {secs:.1f} s net of one call's set-up)",
+            "value_1_thread": ups1,
+            "sample_1_thread": f"{steps1} Heun step(s) of the {share.nx}x{share.ny} grid with {share_M} of the "
+                               f"ordinates on one thread ({secs1:.1f} s)"}
 
 
-def time_workload(p, workload, steps, warmup=3):
-    """Heun steps of another full-size workload on the same kernels: per-step
-    time, updates/s and the two stage kernels' algorithmic rates."""
+def time_workload(p, workload, steps, warmup=3, kernel_steps=None):
+    """Heun steps of a full-size workload: wall-clock time of exactly `steps`
+    steps with no per-launch instrumentation (ms_per_step, updates/s, the
+    step's algorithmic rate), then the two stage kernels' average durations
+    from HIP events on the launch stream over a second pass of
+    `kernel_steps` steps."""
     import torch
 
     from paper_2505_17284_amd import solver
 
+    kernel_steps = kernel_steps or steps
     print(f"[bench] {workload}: {p.name} {steps} steps", file=sys.stderr, flush=True)
     plan = solver.Plan(p, device="cuda:0")
     try:
         plan.run(warmup, unbounded=True)
         torch.cuda.synchronize()
-        plan.set_timing(True)
         t0 = time.perf_counter()
         plan.run(steps, unbounded=True)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
+        plan.set_timing(True)
+        plan.run(kernel_steps, unbounded=True)
+        torch.cuda.synchronize()
         ms, counts = plan.kernel_ms()
         plan.set_timing(False)
         info = plan.info
@@ -159,20 +185,23 @@ def time_workload(p, workload, steps, warmup=3):
     s1 = ms[1] / max(counts[1], 1)
     b2 = algorithmic_bytes(p, info, 2)
     b1 = algorithmic_bytes(p, info, 1)
+    step_gbs = (b1 + b2) / (secs / steps) / 1e9
     return {"workload": workload, "steps": steps, "ms_per_step": secs * 1e3 / steps,
             "updates_per_s": p.cell_ordinates * steps / secs, "stage2_kernel_ms": s2,
             "stage2_achieved_GBs": b2 / (s2 * 1e-3) / 1e9, "stage2_frac": b2 / (s2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "stage1_kernel_ms": s1, "stage1_achieved_GBs": b1 / (s1 * 1e-3) / 1e9,
-            "step_algorithmic_GBs": (b1 + b2) / (secs / steps) / 1e9,
-            "ordinates_per_group": [info["group_size"], info["group_size_average"]]}
+            "stage1_frac": b1 / (s1 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernel_steps": kernel_steps, "step_algorithmic_GBs": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
+            "step_algorithmic_bytes": b1 + b2, "stage1_bytes": b1, "stage2_bytes": b2,
+            "ordinates_per_group": [info["group_size"], info["group_size_average"]], "info": info}
 
 
-def time_cavity(steps, dtype, warmup=3):
-    """The full-size walled cavity (1300^2 cells, 512 ordinates, 3.5 GB per
-    FP32 psi buffer): a state far larger than the 256 MB Infinity Cache."""
+def time_lattice(steps, dtype, warmup=3):
+    """The 700^2 lattice with 256 ordinates (minmod, Heun): 0.5 GB per FP32
+    psi buffer, partly held by the 256 MB Infinity Cache."""
     from paper_2505_17284_amd import inputs as I
 
-    return time_workload(I.config(3).replace(psi_dtype=dtype), "cavity1300_M512_heun2", steps, warmup)
+    return time_workload(I.config(2).replace(psi_dtype=dtype), "lattice700_M256_heun2", steps, warmup)
 
 
 def time_tessellation(steps, dtype, N=22, warmup=2):
@@ -186,7 +215,7 @@ def time_tessellation(steps, dtype, N=22, warmup=2):
 
 
 def time_hohlraum(steps, dtype, n=1300, M=256, warmup=2):
-    """The Hohlraum (Sec. 3.2.1) at n^2 cells with every QoI on: the four
+    """The Hohlraum (layout Sec. 3.2.1, QoIs Sec. 3.2.2) at n^2 cells with every QoI on: the four
     probes' windows (QoI-1) and the fluence behind QoI-3 to QoI-6, timed
     against the same solve without them."""
     import torch
@@ -278,11 +307,16 @@ def time_shard(steps, dtype, shards=8, warmup=3):
     return out
 
 
+HEADLINE = "cavity1300_M512_heun2"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=640)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--kernel-steps", type=int, default=20,
+                    help="steps of the second, event-timed pass that gives the per-kernel averages")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--group", type=int, default=0, help="ordinates per workgroup, both stages (0: default)")
     ap.add_argument("--group-avg", type=int, default=0, help="ordinates per workgroup of the averaging stage")
@@ -291,12 +325,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--uq", type=int, default=256,
                     help="instances of the batched UQ workload (0 skips it)")
-    ap.add_argument("--serving-requests", type=int, default=24,
-                    help="requests of the serving comparison (0 skips it)")
-    ap.add_argument("--serving-load", type=float, default=0.9,
-                    help="arrival rate as a fraction of the one-at-a-time capacity")
-    ap.add_argument("--cavity-steps", type=int, default=40,
-                    help="Heun steps timed on the full-size walled cavity, 1300^2 x 512 ordinates (0 skips it)")
+    ap.add_argument("--serving-requests", type=int, default=32,
+                    help="requests per rate of the serving sweep (0 skips it)")
+    ap.add_argument("--serving-loads", default="0.5,0.9,1.1",
+                    help="arrival rates of the serving sweep as fractions of the one-at-a-time capacity")
+    ap.add_argument("--lattice-steps", type=int, default=100,
+                    help="Heun steps timed on the 700^2 x 256 lattice (0 skips it)")
     ap.add_argument("--tess-steps", type=int, default=10,
                     help="Heun steps timed on the 700^2 lattice with the tessellation quadrature, "
                          "N = 22 (1936 ordinates; 0 skips it)")
@@ -309,6 +343,8 @@ def main():
     ap.add_argument("--shard-steps", type=int, default=40,
                     help="Heun steps timed on one GPU's share of an 8-way ordinate split of the cavity, "
                          "1300^2 x 64 ordinates (0 skips it)")
+    ap.add_argument("--other-dtype", action="store_true",
+                    help="also time the headline workload with the other psi storage type")
     ap.add_argument("--stream-mib", type=int, default=1024,
                     help="MiB per array of the streaming-ceiling measurement (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -325,7 +361,7 @@ def main():
     from paper_2505_17284_amd import inputs as I
     from paper_2505_17284_amd import solver
 
-    problem = I.config(2).replace(psi_dtype=args.dtype)
+    problem = I.config(3).replace(psi_dtype=args.dtype)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     plan = solver.Plan(problem, group_size=args.group, rows_per_wave=args.rows, waves_per_group=args.waves,
@@ -334,15 +370,19 @@ def main():
     print(f"[bench] plan: {info}", file=sys.stderr, flush=True)
     plan.run(args.warmup, unbounded=True)
     torch.cuda.synchronize()
-    plan.set_timing(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.run(args.steps, unbounded=True)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {secs:.4f} s", file=sys.stderr, flush=True)
+    # second pass: per-launch HIP events on the launch stream
+    plan.set_timing(True)
+    plan.run(args.kernel_steps, unbounded=True)
+    torch.cuda.synchronize()
     ms, counts = plan.kernel_ms()
     plan.set_timing(False)
-    print(f"[bench] timed {args.steps} steps in {secs:.4f} s; kernel ms {ms} counts {counts}",
+    plan.close()
+    print(f"[bench] kernel pass: {args.kernel_steps} steps, kernel ms {ms} counts {counts}",
           file=sys.stderr, flush=True)
 
     ups = problem.cell_ordinates * args.steps / secs
@@ -350,13 +390,15 @@ def main():
     avg_ms = ms[kind] / max(counts[kind], 1)
     bytes_launch = algorithmic_bytes(problem, info, kind)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    stage1_bytes = algorithmic_bytes(problem, info, 1)
     stage1_ms = ms[1] / max(counts[1], 1)
-    stage1_gbs = algorithmic_bytes(problem, info, 1) / (stage1_ms * 1e-3) / 1e9
-    step_bytes = algorithmic_bytes(problem, info, 1) + algorithmic_bytes(problem, info, 2)
+    stage1_gbs = stage1_bytes / (stage1_ms * 1e-3) / 1e9
+    step_bytes = stage1_bytes + bytes_launch
+    step_gbs = step_bytes / (secs / args.steps) / 1e9
     traffic = None
     default_shape = not (args.group or args.group_avg or args.rows or args.waves)
     if default_shape:
-        traffic = measured_traffic(args.dtype)
+        traffic = measured_traffic(HEADLINE, args.dtype)
     line = {
         "metric": "cell-ordinate updates/s",
         "value": ups,
@@ -370,24 +412,28 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": "lattice700_M256_heun2", "nx": problem.nx, "ny": problem.ny,
+        "config": {"workload": HEADLINE, "nx": problem.nx, "ny": problem.ny,
                    "ordinates": problem.M, "order": problem.order, "stepper": "heun",
-                   "cfl": problem.cfl, "psi_storage": args.dtype,
+                   "cfl": problem.cfl, "n_steps_to_T": info["n_steps"], "psi_storage": args.dtype,
                    "group_size": info["group_size"], "group_size_average": info["group_size_average"],
                    "rows_per_wave": info["rows_per_wave"],
                    "waves_per_group": info["waves_per_group"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sn_stage_kernel<2, kAverage> (Heun stage 2)",
-                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel_avg_ms": avg_ms, "kernel_launches_timed": counts[kind],
+                     "algorithmic_bytes_per_launch": bytes_launch,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
                                      "calibrated on a device copy)",
                      "traffic_over_algorithmic": None if traffic is None else traffic / bytes_launch},
-        "stage1": {"kernel_avg_ms": stage1_ms, "achieved_GBs": stage1_gbs},
-        "step_algorithmic_GBs": step_bytes / (secs / args.steps) / 1e9,
+        "step_roofline": {"bound": "hbm", "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": step_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_step": step_bytes,
+                          "note": "both stages' algorithmic bytes over the wall-clock ms_per_step "
+                                  "(finalize launches and gaps included)"},
+        "stage1": {"kernel_avg_ms": stage1_ms, "achieved_GBs": stage1_gbs, "frac": stage1_gbs / HBM_PEAK_GBS,
+                   "algorithmic_bytes_per_launch": stage1_bytes},
         "roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / (step_bytes / problem.cell_ordinates),
     }
-    plan.close()
     if args.stream_mib:
         ceil = stream_ceiling(args.stream_mib)
         line["stream_ceiling"] = ceil
@@ -402,26 +448,36 @@ def main():
         torch.cuda.synchronize()
         line["calibration_copy_bytes"] = n
         del src, dst
-    if args.cavity_steps:
-        line["cavity"] = time_cavity(args.cavity_steps, args.dtype)
+    if args.other_dtype:
+        other = "bf16" if args.dtype == "f32" else "f32"
+        line[f"cavity_{other}"] = time_workload(I.config(3).replace(psi_dtype=other), HEADLINE + f"_{other}",
+                                                min(args.steps, 40), 3, args.kernel_steps)
+        line[f"cavity_{other}"].pop("info")
+    if args.lattice_steps:
+        line["lattice700"] = time_lattice(args.lattice_steps, args.dtype)
+        line["lattice700"].pop("info")
     if args.tess_steps:
         line["tessellation"] = time_tessellation(args.tess_steps, args.dtype)
+        line["tessellation"].pop("info")
     if args.venkat_steps:
         line["venkat"] = time_venkat(args.venkat_steps, args.dtype)
+        line["venkat"].pop("info", None)
     if args.hohlraum_steps:
         line["hohlraum"] = time_hohlraum(args.hohlraum_steps, args.dtype)
     if args.shard_steps:
         line["shard_share"] = time_shard(args.shard_steps, args.dtype)
+        line["shard_share"].pop("info")
     from paper_2505_17284_amd import serve
 
     if args.uq:
         print(f"[bench] batched UQ: {args.uq} lattice draws", file=sys.stderr, flush=True)
         line["batched_uq"] = serve.uq(args.uq, verbose=True, tune=True, compare_default=True)
     if args.serving_requests:
-        print(f"[bench] serving: {args.serving_requests} requests at load {args.serving_load}",
-              file=sys.stderr, flush=True)
-        line["serving"] = serve.sweep(args.serving_requests, rates=(args.serving_load,), verbose=False)
+        loads = tuple(float(x) for x in args.serving_loads.split(","))
+        print(f"[bench] serving: {args.serving_requests} requests at loads {loads}", file=sys.stderr, flush=True)
+        line["serving"] = serve.sweep(args.serving_requests, rates=loads, verbose=False)
     if not args.no_cpu:
+        print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(line), flush=True)
 

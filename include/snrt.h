@@ -64,7 +64,9 @@ typedef int32_t sn_status;
 #define SN_HEUN 1
 
 #define SN_F32 0  /* psi stored as IEEE binary32 */
-#define SN_BF16 1 /* psi stored as bfloat16 (round to nearest even), math in FP32 */
+#define SN_BF16 1 /* psi stored as bfloat16, math in FP32; every stored value is
+                   * rounded stochastically (unbiased) with reproducible bits
+                   * drawn from (stage, ordinate, cell) */
 
 /* One cell of a space-time probe (see sn_problem). */
 typedef struct sn_probe_cell {
@@ -99,7 +101,7 @@ typedef struct sn_probe_cell {
  *                 inflow through each rectangle's boundary are QoIs.
  *  psi_dtype      SN_F32 or SN_BF16.
  *  n_probes, n_windows, n_probe_cells, probe_cells
- *                 space-time probes (Hohlraum QoI-1, Sec. 3.2.1): probe p
+ *                 space-time probes (Hohlraum QoI-1, Sec. 3.2.2): probe p
  *                 averages phi = sum_k w_k psi_k, J_x = sum_k w_k xi_k psi_k and
  *                 J_y = sum_k w_k eta_k psi_k over its cells, weighted by
  *                 probe_cells[].weight (the cell's share of the probe region,
@@ -120,7 +122,7 @@ typedef struct sn_probe_cell {
  *  fluence        1: also accumulate the fluence Phi = int_0^t phi dt per cell
  *                 in FP64, with the stepper's time rule (Euler dt phi(psi^n);
  *                 Heun dt/2 (phi(psi^n) + phi(psi^(1)))); the Hohlraum QoI-3
- *                 to QoI-6 (Sec. 3.2.1) are functionals of sigma_a Phi. Costs
+ *                 to QoI-6 (Sec. 3.2.2) are functionals of sigma_a Phi. Costs
  *                 8 nx ny bytes of scratch and 20 bytes of traffic per cell and
  *                 stage. 0: off.
  */
@@ -272,7 +274,7 @@ typedef struct sn_fluence_piece {
 } sn_fluence_piece;
 
 /* Block and line functionals of the fluence (Hohlraum QoI-3 to QoI-6,
- * Sec. 3.2.1), computed on the device in FP64 in a fixed order. All three
+ * Sec. 3.2.2), computed on the device in FP64 in a fixed order. All three
  * arrays are DEVICE memory owned by the caller (the library allocates
  * nothing):
  *  pieces[n_pieces] sorted by set; set g holds pieces [set_start[g],
@@ -310,12 +312,16 @@ void sn_plan_destroy(sn_plan *plan);
 /* ------------------------------------------------------------------ batches
  * Many independent solves advanced together (the batched uncertainty-
  * quantification and serving workloads built on the benchmarks of Sec. 3 with
- * the parameter draws of Sec. 3.1.2 / DP-2): every admitted plan keeps its own
- * state in its own device buffers; each stage of all unfinished plans runs as
- * ONE persistent launch whose workgroups stride over the concatenated tiles
- * of the instances, followed by one batched QoI/phi finalize. Per plan the
- * arithmetic is that of sn_plan_run, so a plan's results are the same alone
- * and in any mix (bit for bit).
+ * the parameter draws of Sec. 3.1.3, DP-2): every admitted plan keeps its own
+ * state in its own device buffers. Each stage of the unfinished plans that
+ * are too small to fill the GPU on their own runs as one batched launch whose
+ * workgroups step over the concatenated tiles of those instances (one
+ * workgroup per tile by default, or a persistent grid, see
+ * workgroups_per_cu), followed by one batched QoI/phi finalize; plans with at
+ * least direct_min_workgroups workgroups per stage take their stages as
+ * launches of their own in the same run. Per plan the arithmetic is that of
+ * sn_plan_run, so a plan's results are the same alone and in any mix (bit
+ * for bit), reading its QoIs mid-run included.
  *
  * Ownership: the batch owns host state only. Its device tables live in a
  * caller-provided workspace of sn_batch_workspace_bytes(opts) bytes (256-byte

@@ -6,7 +6,7 @@ never does.
 
 The fluence is the time integral of the scalar flux per cell, Phi = int_0^T
 phi dt (``oracle.solve(..., fluence=True)``); the discrete solution is constant
-on each cell. The four QoIs of the Hohlraum benchmark (Sec. 3.2.1) integrate
+on each cell. The four QoIs of the Hohlraum benchmark (Sec. 3.2.2) integrate
 a(x, y) = sigma_a(x, y) Phi(x, y) over the green capsule band:
 
   QoI-3  A_G = (1/N_G) sum_i A_i, with A_i the mean of a over green block g_i

@@ -24,7 +24,7 @@
  *   - QoIs: mass (QoI-5), absorption per region (QoI-3/4), outflow through the
  *     boundary of a rectangle (QoI-1/2): Sec. 3.1.2.
  *   - optional: the time integral of phi per cell (fluence) and space-time
- *     probe averages of phi, J_x, J_y (the Hohlraum QoIs of Sec. 3.2.1).
+ *     probe averages of phi, J_x, J_y (the Hohlraum QoIs of Sec. 3.2.2).
  * The readings taken where the paper is silent (minmod reconstruction on the
  * Cartesian grid, reflective walls, the time rule for integrated QoIs, the
  * boundary-slope rule) are listed in the design notes and restated where they
@@ -327,7 +327,7 @@ void orc_qoi(const orc_problem *P, const double *psi, const double *phi, double 
  * qint accumulates the time integral of the QoI vector with the rule that
  * matches the stepper: Euler dt q(psi^n); Heun dt/2 (q(psi^n) + q(psi1)).
  * fluence (NULL to skip) accumulates the time integral of phi per cell,
- * [ny][nx], with the same rule; the Hohlraum QoI-3 to QoI-6 (Sec. 3.2.1)
+ * [ny][nx], with the same rule; the Hohlraum QoI-3 to QoI-6 (Sec. 3.2.2)
  * integrate sigma_a times it over blocks and a line.
  * Returns 0, or -1 if memory could not be allocated. */
 static void add_fluence(const orc_problem *P, double coef, const double *phi, double *fluence)
@@ -337,7 +337,7 @@ static void add_fluence(const orc_problem *P, double coef, const double *phi, do
     for (c = 0; c < ncell; ++c) fluence[c] += coef * phi[c];
 }
 
-/* Space-time probes (Hohlraum QoI-1, Sec. 3.2.1): probe p averages phi,
+/* Space-time probes (Hohlraum QoI-1, Sec. 3.2.2): probe p averages phi,
  * J_x = sum_l w_l xi_l psi_l and J_y = sum_l w_l eta_l psi_l over its cells
  * with the given weights (area of the cell inside the probe's ball over the
  * ball's area) and over each of n_windows equal time windows of [0, T]. A

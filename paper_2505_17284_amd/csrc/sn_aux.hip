@@ -185,7 +185,10 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
         a.inst[s] = tot;
         a.integ[s] += a.coef * tot;
         if (!isfinite(tot)) a.flags[0] = 1;
-        if (s == 0) a.counter[0] += 1;  // one finalize per stage; the next stage reads it
+        // one finalize per stage; the next stage reads it. The QoI-only pass
+        // (no phi partials) is no stage and leaves the count alone, so that
+        // reading QoIs mid-run does not change later rounding bits.
+        if (s == 0 && a.n_phi_wg > 0) a.counter[0] += 1;
         if (a.n_probes > 0 && s >= a.qprobe) {
             // a probe moment: also into the window of the step (this block
             // owns the slot's step counter)

@@ -1,4 +1,4 @@
-"""Hohlraum QoIs laid out on the host (Sec. 3.2.1): the QoI-1 probes and the
+"""Hohlraum QoIs laid out on the host (Sec. 3.2.2; layout Sec. 3.2.1): the QoI-1 probes and the
 green-band QoI-3 to QoI-6.
 
 QoI-1 averages phi, J_x and J_y over a ball of radius 0.01 around each of

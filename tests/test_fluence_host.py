@@ -1,6 +1,6 @@
 """Host side of the fluence functionals: the green-band geometry that the
 device sums over (no GPU). Evaluating the product's pieces with numpy must
-give the oracle's QoI-3 to QoI-6 (Sec. 3.2.1) on aligned and unaligned grids;
+give the oracle's QoI-3 to QoI-6 (Sec. 3.2.2) on aligned and unaligned grids;
 the weights of every block and of the line sum to one."""
 
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the oracle's fluence and of its Hohlraum QoI-3 to QoI-6 (Sec. 3.2.1).
+"""Pins of the oracle's fluence and of its Hohlraum QoI-3 to QoI-6 (Sec. 3.2.2).
 
 The fluence Phi = int_0^T phi dt is pinned by a closed form (the homogeneous
 medium under forward Euler, where phi obeys a scalar linear recurrence) and by

@@ -4,7 +4,7 @@ the GPU, through the C ABI, against the FP64 oracle.
 The device adds coef * phi(stage input) per cell in the QoI finalize of every
 stage; the oracle adds the same time rule to its FP64 phi. Elementwise the
 two agree to the field tolerance of the stages run; the green-band
-functionals (QoI-3 to QoI-6, Sec. 3.2.1) of the device fluence, summed on the
+functionals (QoI-3 to QoI-6, Sec. 3.2.2) of the device fluence, summed on the
 device, agree with the oracle's functionals of its own fluence to the QoI
 tolerance. A batch member accumulates the same fluence bit for bit.
 """

@@ -1,4 +1,4 @@
-"""Space-time probes (Hohlraum QoI-1, Sec. 3.2.1) on the GPU, through the C
+"""Space-time probes (Hohlraum QoI-1, Sec. 3.2.2) on the GPU, through the C
 ABI, against the FP64 oracle.
 
 The stage kernels' loader wave sums phi, J_x and J_y of the stage input over

@@ -1,4 +1,4 @@
-"""Pins of the oracle's space-time probes (Hohlraum QoI-1, Sec. 3.2.1).
+"""Pins of the oracle's space-time probes (Hohlraum QoI-1, Sec. 3.2.2).
 
 The probe weights are pinned by closed-form areas of a disc cut by the grid;
 the window averages by the homogeneous medium under Euler (phi in closed
