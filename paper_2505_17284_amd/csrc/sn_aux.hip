@@ -86,9 +86,14 @@ __global__ void __launch_bounds__(256) sn_ghost_fill_kernel(const GhostArgs a) {
 }
 
 // ---------------------------------------------------------------- finalize
-// Workgroups [0, nq): one per QoI slot; sums the per-workgroup partials in a
-// fixed order (deterministic), scales, and accumulates the time integral.
-// Workgroups [nq, nq + n_phi_wg): phi = sum over groups of the stage's
+// Workgroups [0, nq q_split): QoI slot s = blk / q_split, chunk blk % q_split
+// of its per-workgroup partials (kQoiChunk of them, 8 per thread, all loads
+// in flight at once), summed in a fixed order; with more than one chunk, the
+// chunk that finishes last (a device-scope counter per slot) adds the chunk
+// sums in chunk order. Either way the slot's total is scaled and accumulated
+// into the time integral by one thread. The order of every sum is fixed, so
+// the result does not depend on which chunk finishes last.
+// Workgroups [nq q_split, + n_phi_wg): phi = sum over groups of the stage's
 // partial scalar fluxes, in group order, for every interior cell (4 padded
 // columns per thread, ny * pitch / 4 threads), first adding the replaced phi
 // (the stage input's) to the fluence when that is kept. The QoI slots of the
@@ -107,12 +112,34 @@ __device__ double block_sum(double v, double* red) {
     return red[0];
 }
 
+// The total of QoI slot s: scaled, stored, integrated in time.
+__device__ __forceinline__ void finish_slot(FArgs a, int s, double sum) {
+    const double tot = sum * a.scale[s];
+    a.inst[s] = tot;
+    a.integ[s] += a.coef * tot;
+    if (!isfinite(tot)) a.flags[0] = 1;
+    // one finalize per stage; the next stage reads it. The QoI-only pass
+    // (no phi partials) is no stage and leaves the count alone, so that
+    // reading QoIs mid-run does not change later rounding bits.
+    if (s == 0 && a.n_phi_wg > 0) a.counter[0] += 1;
+    if (a.n_probes > 0 && s >= a.qprobe) {
+        // a probe moment: also into the window of the step (this slot's
+        // finishing thread owns the slot's step counter)
+        const int q = s - a.qprobe;
+        const int32_t step = a.pstep[q];
+        const int64_t w = (int64_t)step * a.n_windows / a.nt;
+        if (w < a.n_windows) a.pacc[(w * a.n_probes + q / 3) * 3 + q % 3] += a.pcoef * tot;
+        if (a.last_stage) a.pstep[q] = step + 1;
+    }
+}
+
 __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
-    if (blk >= a.nq) {
+    const int nqb = a.nq * a.q_split;
+    if (blk >= nqb) {
         // four consecutive padded columns per thread (16-byte aligned: the
         // pitch is a multiple of 16 elements); only interior cells are written
         const int per_row = a.pitch / 4;
-        const int64_t u = (int64_t)(blk - a.nq) * 256 + threadIdx.x;
+        const int64_t u = (int64_t)(blk - nqb) * 256 + threadIdx.x;
         if (u >= (int64_t)a.ny * per_row) return;
         const int j = (int)(u / per_row), c4 = (int)(u - (int64_t)j * per_row);
         const int64_t off = (int64_t)(j + kGhost) * a.pitch + 4 * c4;
@@ -158,18 +185,17 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
         }
         return;
     }
-    const int s = blk;
-    // eight independent accumulators per thread, combined in a fixed order
+    const int s = blk / a.q_split;
+    const int chunk = blk - s * a.q_split;
+    const int lo = chunk * kQoiChunk;
+    const int hi = min(lo + kQoiChunk, a.n_wg);
+    // eight independent loads per thread, combined in a fixed order
     const double* qp = a.qpart + (int64_t)s * a.n_wg;
     double acc8[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc8[u] = 0.0;
-    for (int w0 = threadIdx.x; w0 < a.n_wg; w0 += 256 * 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int w = w0 + u * 256;
-            if (w < a.n_wg) acc8[u] += qp[w];
-        }
+    for (int u = 0; u < 8; ++u) {
+        const int w = lo + (int)threadIdx.x + u * 256;
+        acc8[u] = w < hi ? qp[w] : 0.0;
     }
     double acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
     __shared__ double red[256];
@@ -180,25 +206,23 @@ __device__ __forceinline__ void finalize_block(FArgs a, int blk) {
         if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double tot = red[0] * a.scale[s];
-        a.inst[s] = tot;
-        a.integ[s] += a.coef * tot;
-        if (!isfinite(tot)) a.flags[0] = 1;
-        // one finalize per stage; the next stage reads it. The QoI-only pass
-        // (no phi partials) is no stage and leaves the count alone, so that
-        // reading QoIs mid-run does not change later rounding bits.
-        if (s == 0 && a.n_phi_wg > 0) a.counter[0] += 1;
-        if (a.n_probes > 0 && s >= a.qprobe) {
-            // a probe moment: also into the window of the step (this block
-            // owns the slot's step counter)
-            const int q = s - a.qprobe;
-            const int32_t step = a.pstep[q];
-            const int64_t w = (int64_t)step * a.n_windows / a.nt;
-            if (w < a.n_windows) a.pacc[(w * a.n_probes + q / 3) * 3 + q % 3] += a.pcoef * tot;
-            if (a.last_stage) a.pstep[q] = step + 1;
-        }
+    if (threadIdx.x != 0) return;
+    const double csum = red[0];
+    if (a.q_split == 1) {
+        finish_slot(a, s, csum);
+        return;
     }
+    // Publish the chunk sum, then count it; the chunk that brings the count to
+    // q_split sees every chunk sum (release before the count, acquire after)
+    // and resets the count for the next launch.
+    double* cs = a.qchunk + (int64_t)s * a.q_split;
+    __hip_atomic_store(cs + chunk, csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int done = __hip_atomic_fetch_add(a.qcount + s, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done != a.q_split - 1) return;
+    double tot = 0.0;
+    for (int c = 0; c < a.q_split; ++c) tot += __hip_atomic_load(cs + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.qcount + s, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    finish_slot(a, s, tot);
 }
 
 __global__ void __launch_bounds__(256) sn_qoi_finalize_kernel(const FinalizeArgs a) {
@@ -327,7 +351,7 @@ hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq + a.n_phi_wg), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sn_qoi_finalize_kernel, dim3(a.nq * a.q_split + a.n_phi_wg), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

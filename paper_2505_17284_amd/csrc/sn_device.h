@@ -35,6 +35,10 @@ constexpr int kMaxQWave = 1 + kMaxTallies + 2 * kMaxRects;
 constexpr int kMaxQ = kMaxQWave + 3 * kMaxProbes;
 constexpr int kMaxFluenceBlocks = 1024;
 constexpr int kProbePerLane = 8;  // probe cells one loader lane accumulates
+// Per-workgroup QoI partials one finalize workgroup sums (256 threads x 8):
+// a QoI slot with more partials is summed in ceil(n_wg / kQoiChunk) chunks
+// whose sums the last of them adds up in chunk order.
+constexpr int kQoiChunk = 2048;
 
 enum StageMode : int {
     kUpdate = 0,   // psi_out = psi_in + dt F(psi_in)                   (Euler, Heun stage 1)
@@ -147,6 +151,9 @@ struct FinalizeArgs {
     const double* scale;    // [nq]
     double* inst;           // [nq] instantaneous QoIs of the stage input
     double* integ;          // [nq] running time integrals
+    double* qchunk;         // [nq][q_split] chunk sums (q_split > 1)
+    int32_t* qcount;        // [nq] chunks finished so far in this launch (0 between launches)
+    int32_t q_split;        // chunks per QoI slot: ceil(n_wg / kQoiChunk)
     int32_t* flags;         // bit 0: a non-finite QoI was seen
     int32_t* counter;       // stages finalised so far (incremented once per finalize)
     double coef;            // weight of this stage in the time integral

@@ -61,7 +61,8 @@ struct sn_plan {
     int ntx = 0, nty = 0, nq = 0;
     size_t elem = 4, psi_bytes = 0, scratch_bytes = 0;
     size_t off_phi = 0, off_phi_part = 0, off_ord = 0, off_reg = 0, off_region = 0, off_qpart = 0,
-           off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0;
+           off_scale = 0, off_inst = 0, off_integ = 0, off_mass0 = 0, off_flags = 0, off_qchunk = 0,
+           off_qcount = 0;
     // fluence (time integral of phi per cell, FP64 [ny][nx]) and what its
     // functionals read: sigma_a in FP64 and a status word
     bool fluence = false;

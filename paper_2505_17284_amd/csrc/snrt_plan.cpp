@@ -360,6 +360,10 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     off += align256((size_t)P->plane);
     P->off_qpart = off;
     off += align256((size_t)P->nq * P->n_wg * sizeof(double));
+    P->off_qchunk = off;
+    off += align256((size_t)P->nq * ((P->n_wg + kQoiChunk - 1) / kQoiChunk) * sizeof(double));
+    P->off_qcount = off;
+    off += align256(kMaxQ * sizeof(int32_t));
     P->off_scale = off;
     off += align256(kMaxQ * sizeof(double));
     P->off_inst = off;
@@ -487,8 +491,9 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
 }
 
 int snh::finalize_workgroups(const sn_plan* P, int kind) {
+    const int l = kind == 2 ? 1 : 0;
     const int phi_wg = kind < 0 ? 0 : (int)(((int64_t)P->ny * (P->pitch / 4) + 255) / 256);
-    return P->nq + phi_wg;
+    return P->nq * ((P->n_wg_l[l] + kQoiChunk - 1) / kQoiChunk) + phi_wg;
 }
 
 FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
@@ -507,6 +512,9 @@ FinalizeArgs snh::finalize_args(const sn_plan* P, int kind) {
     f.scale = P->sp<double>(P->off_scale);
     f.inst = P->sp<double>(P->off_inst);
     f.integ = P->sp<double>(P->off_integ);
+    f.qchunk = P->sp<double>(P->off_qchunk);
+    f.qcount = P->sp<int32_t>(P->off_qcount);
+    f.q_split = (P->n_wg_l[l] + kQoiChunk - 1) / kQoiChunk;
     f.flags = P->sp<int32_t>(P->off_flags);
     f.counter = P->sp<int32_t>(P->off_flags) + 1;
     f.coef = kind == 0 ? P->dt : (kind > 0 ? 0.5 * P->dt : 0.0);
@@ -764,6 +772,7 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_integ), 0, kMaxQ * sizeof(double), s), "clear integrals");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_inst), 0, kMaxQ * sizeof(double), s), "clear QoIs");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_flags), 0, 2 * sizeof(int32_t), s), "clear flags and stage counter");
+    HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_qcount), 0, kMaxQ * sizeof(int32_t), s), "clear QoI chunk counts");
     HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_phi), 0, P->plane * sizeof(float), s), "clear phi");
     HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_sa64), P->sa.data(), P->n_regions * sizeof(double),
                            hipMemcpyHostToDevice, s), "upload sigma_a");
