@@ -227,6 +227,28 @@ sn_status sn_plan_get_info(const sn_plan *plan, sn_plan_info *out);
  * plan is destroyed or rebound. */
 sn_status sn_plan_bind(sn_plan *plan, void *psi_a, void *psi_b, void *scratch);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): the same as
+ * sn_plan_bind, with the scratch taken from an area of SN_STATIC_SCRATCH_BYTES
+ * that the library keeps in the memory of every device it is loaded on (held
+ * until the process ends) instead of a caller buffer. psi_a and psi_b are the
+ * caller's, as for sn_plan_bind. The area belongs to the device current at
+ * this call. Allocates nothing: no device allocation or free, and no
+ * allocating library routine.
+ *  - SN_ERR_UNSUPPORTED when the plan's scratch_bytes (sn_plan_get_info)
+ *    exceed SN_STATIC_SCRATCH_BYTES: bind caller-owned scratch instead.
+ *  - SN_ERR_BUSY while another plan is bound to the same device's area: the
+ *    area holds one plan's tables, QoI accumulators and phi at a time; that
+ *    plan must be destroyed or bound elsewhere first. The area keeps what the
+ *    last plan left in it; sn_plan_init resets everything a solve reads
+ *    before writing it.
+ *  - Work of one plan on two streams that overlaps on the device races on the
+ *    area, as it does on caller scratch.
+ * Rebinding the plan (either call) or destroying it frees the area for other
+ * plans. */
+#define SN_STATIC_SCRATCH_BYTES (64 << 20)
+sn_status sn_plan_bind_static(sn_plan *plan, void *psi_a, void *psi_b);
+
 /* Upload the plan's tables, set psi to psi0 (host [M][ny][nx] float32, or
  * NULL for psi0 = 0 as in both benchmarks), reset step and QoI integrals.
  * Asynchronous on `stream`; psi0 is copied before the call returns. */

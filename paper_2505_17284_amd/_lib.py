@@ -24,6 +24,7 @@ SN_ERR_BUSY = 6
 SN_ERR_STATE = 7
 SN_F32 = 0
 SN_BF16 = 1
+STATIC_SCRATCH_BYTES = 64 << 20  # SN_STATIC_SCRATCH_BYTES
 MAX_TALLIES = 8
 MAX_RECTS = 4
 MAX_FLUENCE_BLOCKS = 1024
@@ -36,6 +37,7 @@ MAX_PROBES = 8
 # Every symbol the header declares; tests check the library exports them all.
 EXPORTED = [
     "sn_plan_create", "sn_plan_create_tuned", "sn_plan_create_shaped", "sn_plan_get_info", "sn_plan_bind",
+    "sn_plan_bind_static",
     "sn_plan_init", "sn_plan_run", "sn_plan_run_unbounded", "sn_plan_qoi",
     "sn_plan_read_psi", "sn_plan_read_phi", "sn_plan_read_fluence", "sn_plan_fluence_functionals",
     "sn_plan_read_probes",
@@ -127,6 +129,7 @@ def lib():
         L.sn_plan_create_shaped.argtypes = [ctypes.POINTER(SnProblem), _i32, _i32, _i32, _i32, PP]
         L.sn_plan_get_info.argtypes = [_vp, ctypes.POINTER(SnPlanInfo)]
         L.sn_plan_bind.argtypes = [_vp, _vp, _vp, _vp]
+        L.sn_plan_bind_static.argtypes = [_vp, _vp, _vp]
         L.sn_plan_init.argtypes = [_vp, _vp, _vp]
         L.sn_plan_run.argtypes = [_vp, _i32, _vp]
         L.sn_plan_run_unbounded.argtypes = [_vp, _i32, _vp]

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "sn_stage_o1_f32.hip", "sn_stage_o2_f32.hip", "sn_stage_o1_bf16.hip", "sn_stage_o2_bf16.hip",
     "sn_stage_o3_f32.hip", "sn_stage_o3_bf16.hip",
-    "sn_aux.hip", "snrt_plan.cpp", "snrt_batch.cpp")]
+    "sn_aux.hip", "snrt_plan.cpp", "snrt_batch.cpp", "snrt_static.hip")]
 ARCH = os.environ.get("SNRT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (see the design notes)

@@ -85,6 +85,7 @@ struct sn_plan {
     // device
     char* psi[2] = {nullptr, nullptr};
     char* scratch = nullptr;
+    int static_dev = -1;  // device whose library-held scratch area the plan is bound to, or -1
     bool bound = false, inited = false;
     int64_t step = 0;
     int cur = 0;  // buffer holding the current state
@@ -125,5 +126,10 @@ int finalize_workgroups(const sn_plan* P, int kind);
 // advances P's step counter and buffer parity. Used by a batch for plans
 // that fill the GPU on their own.
 sn_status issue_steps(sn_plan* P, int n, hipStream_t s);
+// Validate and lend buffers to P (the body of sn_plan_bind, without touching
+// a static-scratch binding; P->static_dev becomes -1 on success).
+sn_status bind_buffers(sn_plan* P, void* psi_a, void* psi_b, void* scratch);
+// P no longer holds the library-held scratch area of device dev (snrt_static.hip).
+void release_static_scratch(const sn_plan* P, int dev);
 
 }  // namespace snh

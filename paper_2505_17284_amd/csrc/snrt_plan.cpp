@@ -665,6 +665,25 @@ sn_status run_steps(sn_plan* P, int n, hipStream_t s) {
 
 sn_status snh::issue_steps(sn_plan* P, int n, hipStream_t s) { return launch_steps(P, n, s, false); }
 
+sn_status snh::bind_buffers(sn_plan* P, void* psi_a, void* psi_b, void* scratch) {
+    if (!P || !psi_a || !psi_b || !scratch) return fail(SN_ERR_INVALID, "NULL argument");
+    if (P->batch) return fail(SN_ERR_STATE, "plan is admitted to a batch");
+    const uintptr_t pa = (uintptr_t)psi_a, pb = (uintptr_t)psi_b, ps = (uintptr_t)scratch;
+    if ((pa | pb | ps) & 255) return fail(SN_ERR_INVALID, "device buffers must be 256-byte aligned");
+    auto overlap = [](uintptr_t a, size_t na, uintptr_t b, size_t nb) { return a < b + nb && b < a + na; };
+    if (overlap(pa, P->psi_bytes, pb, P->psi_bytes) || overlap(pa, P->psi_bytes, ps, P->scratch_bytes) ||
+        overlap(pb, P->psi_bytes, ps, P->scratch_bytes))
+        return fail(SN_ERR_INVALID, "device buffers overlap");
+    drop_graph(P);
+    P->psi[0] = (char*)psi_a;
+    P->psi[1] = (char*)psi_b;
+    P->scratch = (char*)scratch;
+    P->static_dev = -1;
+    P->bound = true;
+    P->inited = false;
+    return SN_OK;
+}
+
 extern "C" {
 
 const char* sn_last_error(void) { return snh::last_error(); }
@@ -739,22 +758,13 @@ sn_status sn_plan_get_info(const sn_plan* P, sn_plan_info* out) {
 }
 
 sn_status sn_plan_bind(sn_plan* P, void* psi_a, void* psi_b, void* scratch) {
-    if (!P || !psi_a || !psi_b || !scratch) return fail(SN_ERR_INVALID, "NULL argument");
-    if (P->batch) return fail(SN_ERR_STATE, "plan is admitted to a batch");
-    const uintptr_t pa = (uintptr_t)psi_a, pb = (uintptr_t)psi_b, ps = (uintptr_t)scratch;
-    if ((pa | pb | ps) & 255) return fail(SN_ERR_INVALID, "device buffers must be 256-byte aligned");
-    auto overlap = [](uintptr_t a, size_t na, uintptr_t b, size_t nb) { return a < b + nb && b < a + na; };
-    if (overlap(pa, P->psi_bytes, pb, P->psi_bytes) || overlap(pa, P->psi_bytes, ps, P->scratch_bytes) ||
-        overlap(pb, P->psi_bytes, ps, P->scratch_bytes))
-        return fail(SN_ERR_INVALID, "device buffers overlap");
-    drop_graph(P);
-    P->psi[0] = (char*)psi_a;
-    P->psi[1] = (char*)psi_b;
-    P->scratch = (char*)scratch;
-    P->bound = true;
-    P->inited = false;
-    return SN_OK;
+    if (!P) return fail(SN_ERR_INVALID, "NULL argument");
+    const int old_dev = P->static_dev;
+    const sn_status st = snh::bind_buffers(P, psi_a, psi_b, scratch);
+    if (st == SN_OK && old_dev >= 0) snh::release_static_scratch(P, old_dev);
+    return st;
 }
+
 
 sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     if (!P) return fail(SN_ERR_INVALID, "plan is NULL");
@@ -1056,6 +1066,7 @@ sn_status sn_plan_kernel_ms(sn_plan* P, double ms[4], int64_t counts[4]) {
 
 void sn_plan_destroy(sn_plan* P) {
     if (!P) return;
+    if (P->static_dev >= 0) snh::release_static_scratch(P, P->static_dev);
     drop_graph(P);
     for (auto e : P->ev_start) (void)hipEventDestroy(e);
     for (auto e : P->ev_stop) (void)hipEventDestroy(e);

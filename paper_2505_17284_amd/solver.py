@@ -62,10 +62,12 @@ class Plan:
 
     def __init__(self, problem, group_size: int = 0, rows_per_wave: int = 0, waves_per_group: int = 0,
                  device: str = "cuda:0", psi0=None, graph_steps: int = 0, group_size_average: int = 0,
-                 fluence: bool = False, probes=None):
+                 fluence: bool = False, probes=None, static_scratch: bool = False):
         """fluence: keep the time integral of phi per cell (``fluence()``);
         probes: space-time probes, a dict with n_probes, n_windows and cells
-        (PROBE_CELL records; ``hohlraum.probe_cells`` builds the paper's)."""
+        (PROBE_CELL records; ``hohlraum.probe_cells`` builds the paper's);
+        static_scratch: take the scratch from the library's own device area
+        (sn_plan_bind_static) instead of a PyTorch buffer."""
         torch = _torch()
         assert problem.n_tallies <= MAX_TALLIES and problem.n_rects <= MAX_RECTS
         self.problem = problem
@@ -82,9 +84,14 @@ class Plan:
         with torch.cuda.device(self.device):
             self.psi_a = torch.empty(int(info.psi_bytes), dtype=torch.uint8, device=self.device)
             self.psi_b = torch.empty(int(info.psi_bytes), dtype=torch.uint8, device=self.device)
-            self.scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device=self.device)
-        check(lib().sn_plan_bind(self.h, self.psi_a.data_ptr(), self.psi_b.data_ptr(),
-                                 self.scratch.data_ptr()), "sn_plan_bind")
+            if static_scratch:
+                self.scratch = None
+                check(lib().sn_plan_bind_static(self.h, self.psi_a.data_ptr(), self.psi_b.data_ptr()),
+                      "sn_plan_bind_static")
+            else:
+                self.scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device=self.device)
+                check(lib().sn_plan_bind(self.h, self.psi_a.data_ptr(), self.psi_b.data_ptr(),
+                                         self.scratch.data_ptr()), "sn_plan_bind")
         if graph_steps:
             check(lib().sn_plan_use_graph(self.h, int(graph_steps)), "sn_plan_use_graph")
         self.init(psi0)

@@ -215,3 +215,22 @@ def test_default_launch_shapes(L):
     assert g(I.lattice(140, 256, order=2, stepper=I.HEUN)) == (16, 16, 2, 4)
     assert g(I.lattice(560, 128, order=2, stepper=I.HEUN)) == (32, 32, 2, 4)
     assert g(I.lattice(560, 256, order=2, stepper=I.HEUN)) == (32, 16, 2, 4)
+
+
+def test_static_scratch_rejects_what_it_cannot_hold(L):
+    """sn_plan_bind_static refuses NULL buffers and plans whose scratch exceeds
+    SN_STATIC_SCRATCH_BYTES before touching the device."""
+    lib = L.lib()
+    big = I.config(3)  # 1300^2 x 512: more scratch than the static area holds
+    m = L.MarshalledProblem(big)
+    h = ctypes.c_void_p()
+    assert lib.sn_plan_create(ctypes.byref(m.struct), ctypes.byref(h)) == 0
+    try:
+        info = L.SnPlanInfo()
+        assert lib.sn_plan_get_info(h, ctypes.byref(info)) == 0
+        assert info.scratch_bytes > L.STATIC_SCRATCH_BYTES
+        assert lib.sn_plan_bind_static(h, None, None) == L.SN_ERR_INVALID
+        assert lib.sn_plan_bind_static(h, ctypes.c_void_p(256), ctypes.c_void_p(1 << 40)) == L.SN_ERR_UNSUPPORTED
+        assert "SN_STATIC_SCRATCH_BYTES" in lib.sn_last_error().decode()
+    finally:
+        lib.sn_plan_destroy(h)
