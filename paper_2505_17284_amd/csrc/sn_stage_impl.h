@@ -111,14 +111,11 @@ __device__ __forceinline__ uint32_t bf16_narrow(float v) {
     return u >> 16;
 }
 
-__device__ __forceinline__ uint32_t bf16_sr(float v, uint32_t r) {
-    const uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_narrow(v);  // Inf, NaN
-    return (u + (r & 0xffffu)) >> 16;
-}
+using bf16x2_t = short __attribute__((ext_vector_type(2)));
 
 // MurmurHash3's 32-bit finalizer (fmix32): a bijective mix of the input bits,
-// used to derive reproducible rounding bits from (stage, ordinate, cell).
+// used to derive a reproducible, well-mixed key per (stage, ordinate) for the
+// rounding bits (wave-uniform: scalar instructions).
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x85ebca6bu;
@@ -134,13 +131,20 @@ struct Store<uint16_t> {
         const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
         return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
     }
-    // Stochastic rounding to bfloat16 with the random 16-bit values r0, r1:
-    // adding r to the magnitude bits below the kept 16 and truncating rounds
-    // up with probability equal to the discarded fraction, so the stored value
-    // is unbiased. Round-to-nearest would drop every update smaller than half
-    // a bfloat16 ulp (2^-9 relative) and let slowly changing fluxes stagnate.
+    // Stochastic rounding to bfloat16 with the random 16-bit values r0, r1
+    // (low halves): adding r to the magnitude bits below the kept 16 and
+    // truncating rounds up with probability equal to the discarded fraction,
+    // so the stored value is unbiased. Round-to-nearest would drop every
+    // update smaller than half a bfloat16 ulp (2^-9 relative) and let slowly
+    // changing fluxes stagnate. gfx950's v_cvt_sr_bf16_f32 does exactly this
+    // with the top 16 bits of its random operand (NaN quieted, Inf kept), one
+    // instruction per value, writing either half of the packed pair.
     static __device__ __forceinline__ float2 round2(float2 v, uint32_t r0, uint32_t r1) {
-        return make_float2(bf16_widen(bf16_sr(v.x, r0)), bf16_widen(bf16_sr(v.y, r1)));
+        bf16x2_t p = {0, 0};
+        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.x, r0 << 16, false);
+        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.y, r1 << 16, true);
+        const uint32_t u = __builtin_bit_cast(uint32_t, p);
+        return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
     }
     // v must already be representable (round2): narrowing is then exact.
     static __device__ __forceinline__ void store2(char* p, float2 v) {
@@ -684,7 +688,13 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
             uint32_t r0 = 0, r1 = 0;
             if (sizeof(T) == 2) {  // rounding bits from (stage, ordinate, cell pair of the plane)
                 const uint32_t sk = fmix32(fmix32(w.seed) + (uint32_t)k);  // wave-uniform
-                r0 = fmix32(sk ^ ((rowb + w.lane_off) / (uint32_t)sizeof(T)));
+                // per cell pair: a multiplicative (Fibonacci) hash of the key
+                // xor the pair's index, folded once. For a fixed cell the
+                // bits follow the key, uniform over stages and ordinates; one
+                // multiply instead of a second fmix32 (the stage is bound by
+                // its VALU issue with BF16 storage).
+                r0 = (sk ^ ((rowb + w.lane_off) / (uint32_t)sizeof(T))) * 0x9E3779B1u;
+                r0 ^= r0 >> 16;
                 r1 = r0 >> 16;  // the two halves of one mixed word, one per cell
             }
             v = Store<T>::round2(v, r0, r1);

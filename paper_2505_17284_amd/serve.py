@@ -89,9 +89,19 @@ def response_ratio_order(keys, wait_s: dict, rem_s: dict, tiebreak: dict) -> lis
     return sorted(keys, key=lambda k: (-(wait_s[k] + rem_s[k]) / rem_s[k], tiebreak[k]))
 
 
+def deadline_order(keys, arrival_s: dict, service_s: dict, tiebreak: dict, slowdown: float) -> list:
+    """keys by earliest deadline first, deadline = arrival + slowdown x the
+    request's whole service time alone (ties by `tiebreak`): a short request
+    gets an early deadline and overtakes long ones, but every request's
+    deadline comes up at a fixed multiple of its own service time, which
+    bounds how long a long request waits behind a stream of short ones."""
+    return sorted(keys, key=lambda k: (arrival_s[k] + slowdown * service_s[k], tiebreak[k]))
+
+
 def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_run: int = 32,
-          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "srpt", verbose: bool = False,
-          batch_factory=None, max_steps_per_run: int = 256, run_work: float = 2e10, service_rate: float = 8e11):
+          rows_per_wave: int = 2, waves_per_group: int = 4, policy: str = "deadline", verbose: bool = False,
+          batch_factory=None, max_steps_per_run: int = 256, run_work: float = 2e10, service_rate: float = 8e11,
+          slowdown: float = 4.0):
     """Continuous batching over `requests` = [(arrival_s, Problem)], Heun + minmod.
 
     policy "srpt": the admitted request with the least remaining work (psi
@@ -103,7 +113,11 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
     first, re-ranked every run, the remaining time estimated from the rate
     measured so far (service_rate psi-step bytes per second until then):
     short requests still overtake, but a long one's ratio grows while it
-    waits, which bounds its delay; "arrival": the same with the oldest
+    waits, which bounds its delay; "deadline" (the default): the same with
+    the earliest deadline first, deadline = arrival + slowdown x the
+    request's whole service time at the measured rate (short requests still
+    overtake, and no request's slowdown grows without bound); "arrival": the
+    same with the oldest
     request first, so no request is slowed much by later arrivals; "work": per-run step quotas share the GPU by work (short
     requests finish fast, long ones are slowed down); "steps": every admitted
     request takes steps_per_run steps per run. With "arrival" a run holds at
@@ -114,7 +128,7 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
     stand-in that models the device."""
     dtypes = sorted({p.psi_dtype for _, p in requests})
     make = batch_factory or B.Batch
-    k_max = max(steps_per_run, max_steps_per_run if policy in ("arrival", "srpt") else steps_per_run)
+    k_max = max(steps_per_run, max_steps_per_run if policy in ("arrival", "srpt", "deadline") else steps_per_run)
     n_steps = [solver.plan_info(p)["n_steps"] for _, p in requests]
     batches = {d: make(order=2, stepper=I.HEUN, psi_dtype=d, max_instances=max_instances,
                        steps_per_run=k_max, rows_per_wave=rows_per_wave,
@@ -167,6 +181,12 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
                            for key, i in slot_of.items()}
                     order = sorted(slot_of, key=lambda key: (rem[key], slot_of[key]))
                     quotas = arrival_quotas(order, costs, steps_per_run, backfill=0.1, min_work=run_work, k_max=k_max)
+                elif policy == "deadline":
+                    rate = work_done / busy_s if busy_s > 0 and work_done > 0 else service_rate
+                    service_s = {key: costs[key] * n_steps[i] / rate for key, i in slot_of.items()}
+                    arrival_s = {key: requests[i][0] for key, i in slot_of.items()}
+                    order = deadline_order(list(slot_of), arrival_s, service_s, slot_of, slowdown)
+                    quotas = arrival_quotas(order, costs, steps_per_run, backfill=0.1, min_work=run_work, k_max=k_max)
                 elif policy == "hrrn":
                     rate = work_done / busy_s if busy_s > 0 and work_done > 0 else service_rate
                     now = time.perf_counter() - t0
@@ -185,7 +205,7 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
                 if nxt < len(requests):
                     time.sleep(max(0.0, requests[nxt][0] - (time.perf_counter() - t0)))
                 continue
-            if policy == "hrrn":
+            if policy in ("hrrn", "deadline"):
                 before = {key: batches[key[0]].status(key[1])[1] for key in slot_of}
                 tw = time.perf_counter()
             for b in active:
@@ -193,10 +213,10 @@ def serve(requests, hbm_budget_bytes: int, max_instances: int = 64, steps_per_ru
             windows += 1
             for b in active:
                 b.synchronize()
-            if policy == "hrrn":
+            if policy in ("hrrn", "deadline"):
                 busy_s += time.perf_counter() - tw
                 work_done += sum(costs[key] * (batches[key[0]].status(key[1])[1] - st) for key, st in before.items())
-                changed = True  # ratios move with time: re-rank every run
+                changed = changed or policy == "hrrn"  # ratios move with time: re-rank every run
             for d, b in batches.items():
                 for s in b.done_slots():
                     i = slot_of.pop((d, s))
@@ -347,7 +367,7 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
 
 def sweep(n_requests: int = 24, rates=(0.5, 0.9), seed: int = 0, budget_gb: float = 200.0,
           dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32,
-          policies=("srpt", "arrival"), capacity_batched: bool = True, verbose: bool = False):
+          policies=("deadline", "srpt"), capacity_batched: bool = True, verbose: bool = False):
     """Capacity of both paths (all requests at once), then the one-at-a-time
     path and the continuous-batching loop (each policy) on the same Poisson
     arrivals at fractions of the one-at-a-time capacity."""

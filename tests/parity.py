@@ -1,13 +1,16 @@
 """Comparison helpers for GPU-vs-oracle parity tests.
 
 Tolerances (derivation in the design notes):
-  * QoIs: 1e-5 relative, the FP32 target. The outflow and the inflow through
-    a rectangle are the two halves of the gross current through its boundary,
-    and FP32 resolves each half relative to that gross current (the traces of
-    both directions carry the same absolute rounding), so out:r and in:r are
-    held to 1e-5 of out:r + in:r. QoIs below 1e-6 of the problem's scale
-    (total particles injected or present) are held to 1e-5 of that floor in
-    absolute terms instead.
+  * QoIs: 1e-5 relative, the FP32 target, each QoI of its own value
+    (per_qoi=True: the full benchmark runs). QoIs below 1e-6 of the
+    problem's scale (total particles injected or present) are held to 1e-5
+    of that floor in absolute terms instead (R18).
+    The short random-state cases (per_qoi=False, the default) hold the
+    outflow and the inflow through a rectangle to 1e-5 of out:r + in:r: there
+    the state is noise of unit size, the two halves of the gross current
+    through a rectangle cancel to arbitrary small net values, and FP32
+    resolves each half only relative to the gross current (the traces of
+    both directions carry the same absolute rounding).
   * fields after n stages: |gpu - oracle| <= FIELD_RTOL |oracle| + atol with
     atol = FIELD_ATOL(n) * max|oracle|: FP32 rounding of each stage's update
     is a few ulps of the largest value in the stencil and accumulates at most
@@ -43,8 +46,10 @@ def qoi_scale(inst: dict, integ: dict) -> tuple:
     return s_inst, s_int
 
 
-def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rtol: float = QOI_RTOL):
-    """Returns (ok, report) comparing every named QoI."""
+def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rtol: float = QOI_RTOL,
+                per_qoi: bool = False, rtol_for: dict | None = None):
+    """Returns (ok, report) comparing every named QoI; rtol_for maps QoI names
+    to their own relative tolerance (each derived where it is used)."""
     s_inst, s_int = qoi_scale(orc_inst, orc_int)
     ok = True
     lines = []
@@ -56,12 +61,12 @@ def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rt
             floor = QOI_FLOOR * scale
             err = abs(gv - ov)
             ref = abs(ov)
-            if name.startswith("out:") or name.startswith("in:"):
+            if not per_qoi and (name.startswith("out:") or name.startswith("in:")):
                 r = name.split(":", 1)[1]
                 ref = abs(float(o.get("out:" + r, 0.0))) + abs(float(o.get("in:" + r, 0.0)))
             if ref >= floor:
                 rel = err / ref
-                good = rel <= rtol
+                good = rel <= (rtol_for or {}).get(name, rtol)
                 tag = "" if ref == abs(ov) else " (of gross current)"
                 lines.append(f"{kind:4s} {name:14s} orc={ov:.12g} gpu={gv:.12g} rel={rel:.2e}{tag}{'' if good else '  FAIL'}")
             else:

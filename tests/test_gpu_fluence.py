@@ -177,7 +177,8 @@ def test_functionals_reject_malformed_piece_lists(sv):
 def test_hohlraum260_full_run_green_band_matches_golden(sv):
     """Full Hohlraum solve (260^2, 256 ordinates, minmod, Heun, 1040 steps):
     QoI-3 to QoI-6 against the oracle's values stored by
-    tests/golden/make_oracle_goldens.py."""
+    tests/golden/make_oracle_goldens.py, at 1e-5 (measured: A_G 5e-9, A_L 3e-8,
+    V_G 4e-7, V_L 2e-7, the 44 block means within 3.5e-6)."""
     path = os.path.join(GOLDEN, "oracle_hohlraum260_M256_heun2.json")
     with open(path) as f:
         gold = json.load(f)
@@ -188,4 +189,4 @@ def test_hohlraum260_full_run_green_band_matches_golden(sv):
     gb = dict(gold["green_band"])
     gb["A"] = np.array(gb["A"])
     print({k: (band[k], gb[k]) for k in ("A_G", "V_G", "A_L", "V_L")})
-    _check_band(band, gb, rtol=1e-4)
+    _check_band(band, gb, rtol=1e-5)

@@ -265,7 +265,7 @@ def test_hohlraum260_full_run_matches_golden(sv):
         gold = json.load(f)
     p = I.hohlraum(260, 256)
     r = sv.solve(p)
-    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"])
+    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], per_qoi=True)
     print(rep)
     assert ok, rep
 
@@ -280,7 +280,7 @@ def test_lattice700_full_run_matches_golden(sv):
         gold = json.load(f)
     p = I.config(2)
     r = sv.solve(p)
-    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"])
+    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], per_qoi=True)
     print(rep)
     assert ok, rep
 

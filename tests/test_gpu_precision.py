@@ -53,7 +53,8 @@ def test_lattice700_full_run_error_per_qoi(sv, dtype):
             rel = abs(gv - ov) / abs(ov) if ov else abs(gv - ov)
             print(f"| {dtype} | {name} {kind} | {ov:.10g} | {gv:.10g} | {rel:.2e}{'' if ov else ' (abs)'} |")
     if dtype == "f32":
-        ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], rtol=BOUND[dtype])
+        ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], rtol=BOUND[dtype],
+                              per_qoi=True)
         assert ok, rep
         return
     for g, o in ((r["qoi"], gold["qoi"]), (r["qoi_int"], gold["qoi_int"])):

@@ -121,8 +121,9 @@ def test_probes_batch_and_graph_bit_identical(sv):
 def test_hohlraum260_full_run_probes_match_golden(sv):
     """Full Hohlraum solve (260^2, 256 ordinates, minmod, Heun, 1040 steps):
     QoI-1 (4 probes x 10 windows x phi, J_x, J_y) against the oracle's values
-    stored by tests/golden/make_oracle_goldens.py, to 1e-4 of each probe's
-    phi scale."""
+    stored by tests/golden/make_oracle_goldens.py, each to 1e-5 of itself plus
+    1e-5 of its probe's largest window phi (measured: at most 1.3e-6 of that
+    scale)."""
     from paper_2505_17284_amd import hohlraum
 
     path = os.path.join(GOLDEN, "oracle_hohlraum260_M256_heun2.json")
@@ -138,7 +139,7 @@ def test_hohlraum260_full_run_probes_match_golden(sv):
         g = plan.probes()
     finally:
         plan.close()
-    _compare(g, np.array(gold["probes"]), rtol=1e-4)
+    _compare(g, np.array(gold["probes"]), rtol=1e-5)
 
 
 @pytest.mark.parametrize("order,stepper,dtype,shape,rh", [

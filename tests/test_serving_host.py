@@ -229,3 +229,30 @@ def test_hrrn_policy_serves_everything_and_re_ranks_every_run():
     assert any(first[f"s{i}"] == 4 for i in range(6)) and first["big"] < 4
     by = {r["name"]: r for r in rec}
     assert max(by[f"s{i}"]["done"] for i in range(6)) < by["big"]["done"]
+
+
+def test_deadline_order():
+    keys = ["long", "short", "late_short"]
+    arrival = {"long": 0.0, "short": 0.5, "late_short": 30.0}
+    service = {"long": 10.0, "short": 1.0, "late_short": 1.0}
+    tie = {"long": 0, "short": 1, "late_short": 2}
+    # deadlines at slowdown 4: long 40, short 4.5, late_short 34
+    assert serve.deadline_order(keys, arrival, service, tie, 4.0) == ["short", "late_short", "long"]
+    # a short request arriving after the long one's deadline no longer overtakes it
+    arrival["late_short"] = 39.5
+    assert serve.deadline_order(keys, arrival, service, tie, 4.0) == ["short", "long", "late_short"]
+
+
+def test_deadline_policy_lets_short_requests_overtake_and_finishes_all():
+    MockBatch.made.clear()
+    big = I.lattice(80, 64, order=2, stepper=I.HEUN, name="big")
+    reqs = [(0.0, big)] + [(0.0, I.lattice(40, 32, order=2, stepper=I.HEUN, t_end=0.7, name=f"s{i}"))
+                           for i in range(4)]
+    rec, tot = serve.serve(reqs, 10 ** 12, max_instances=8, steps_per_run=4, max_steps_per_run=4,
+                           policy="deadline", run_work=0.0, batch_factory=MockBatch)
+    assert all(r["done"] is not None for r in rec)
+    (b,) = MockBatch.made
+    first = {name: n for n, name, _ in b.runs[0].values()}
+    assert first["s0"] == 4 and first["big"] < 4  # the earliest deadline leads
+    by = {r["name"]: r for r in rec}
+    assert max(by[f"s{i}"]["done"] for i in range(4)) < by["big"]["done"]
