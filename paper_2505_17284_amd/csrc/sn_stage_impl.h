@@ -338,7 +338,12 @@ struct Ring {
     static constexpr int kHaloRowsPerDma = kWave / kHaloLanesPerRow;
     static constexpr int kDmaHalo = (kHaloRows + kHaloRowsPerDma - 1) / kHaloRowsPerDma;
     static constexpr int kHaloOffset = kSlotRows * kRowBytes;             // bytes into the slot
-    static constexpr int kSlotBytes = kHaloOffset + kDmaHalo * kWave * 4;
+    // Order 3: the loader's trace of the one cell beyond the tile that each
+    // output row's x-faces need (east face of cell -1 when xi > 0, west face
+    // of cell 128 when xi < 0), one float per output row.
+    static constexpr int kEdgeOffset = kHaloOffset + kDmaHalo * kWave * 4;
+    static constexpr int kEdgeBytes = XH > 0 ? (W * TY * 4 + 15) / 16 * 16 : 0;
+    static constexpr int kSlotBytes = kEdgeOffset + kEdgeBytes;
     static constexpr int kDmaPerOrd = kDmaStencil + kDmaOld + kDmaHalo;  // copies per ordinate
     static constexpr int kBytes = kSlots * kSlotBytes;
     // outstanding copies allowed while waiting for the oldest ordinate when
@@ -455,6 +460,38 @@ __device__ __forceinline__ float4 halo_read<uint16_t>(const char* h) {
                        bf16_widen(u.y >> 16));
 }
 
+// Order 3, in the loader wave once ordinate k's rows have landed in `slot`:
+// for every output row q of the workgroup, the trace at the tile's edge that
+// lanes 0 / 63 of the compute waves need and no lane of theirs holds -- the
+// east face of cell -1 (xi > 0) or the west face of cell 128 (xi < 0), the
+// Venkatakrishnan-limited reconstruction of that cell from its staged x-halo
+// and the halo of the rows above and below, evaluated as the compute waves
+// would. One pass of W TY lanes instead of one 64-lane pass per output row in
+// every compute wave.
+using const_ord_ptr = const __attribute__((address_space(4))) OrdConst*;
+
+template <typename T, int TY, int W, int MODE, int XH>
+__device__ __forceinline__ void loader_edges(SArgs a, int k, char* slot) {
+    using R = Ring<T, TY, W, MODE, XH>;
+    const int q = threadIdx.x & (kWave - 1);  // output row of the workgroup
+    const bool sx = (((const_ord_ptr)a.ord + k)->flags & 1) != 0;  // wave-uniform
+    if (q < W * TY) {
+        const float4 hu = halo_read<T>(slot + R::kHaloOffset + q * R::kHaloRowBytes);       // row above
+        const float4 hv = halo_read<T>(slot + R::kHaloOffset + (q + 1) * R::kHaloRowBytes); // the row
+        const float4 hd = halo_read<T>(slot + R::kHaloOffset + (q + 2) * R::kHaloRowBytes); // row below
+        const char* row = slot + (q + 2) * R::kRowBytes;  // the row's staged cells 0 .. 127
+        float e, ax, ay;
+        if (sx) {
+            const float L = venkat_limit(hv.y, hv.x, ring_read<T>(row, 0).x, hu.y, hd.y, a.eps2, ax, ay);
+            e = fmaf(L, ax, hv.y);
+        } else {
+            const float L = venkat_limit(hv.z, ring_read<T>(row, kWave - 1).y, hv.w, hu.z, hd.z, a.eps2, ax, ay);
+            e = fmaf(-L, ax, hv.z);
+        }
+        reinterpret_cast<float*>(slot + R::kEdgeOffset)[q] = e;
+    }
+}
+
 // Stores one cell pair (or the first cell only) at byte offset `off` of plane base `p`.
 template <typename T>
 __device__ __forceinline__ void put_pair(char* p, size_t off, float2 v, bool v0, bool v1) {
@@ -546,7 +583,7 @@ __device__ __forceinline__ void write_frame_all(SArgs a, const OrdConst& o, int 
 template <int ORDER, int MODE, typename T, int TY, int W, bool SX, bool SY>
 __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k, WaveCtx<TY>& w,
                                                const float2 (&win)[TY + 4], const float4 (&halo)[TY + kExtraHalo<ORDER>],
-                                               const float2 (&oldv)[TY], double* facc) {
+                                               const float2 (&oldv)[TY], const float* edge, double* facc) {
     constexpr int D = SY ? 0 : 1;  // y-traces of output row t: Ry[t + 1 + D] (south), Ry[t + 2 + D] (north)
     constexpr float HX = SX ? 0.5f : -0.5f;
     constexpr float HY = SY ? 0.5f : -0.5f;
@@ -578,22 +615,17 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
             }
             if (r >= 2 && r <= TY + 1) {
                 const int t = r - 2;
-                const float4 hu = halo[r - 2], hd = halo[r];  // rows r - 1 and r + 1
+                // the trace of the cell beyond the tile (loader_edges)
+                const float e = edge[t];
                 if (SX) {
-                    // east face of cell -1 (lane 0's left neighbour; its east
-                    // neighbour is lane 0's cell 0)
-                    float axm, aym;
-                    const float Lm = venkat_limit(hv.y, hv.x, c0, hu.y, hd.y, a.eps2, axm, aym);
-                    const float REl = lane_from_left(fmaf(L1, ax1, c1), fmaf(Lm, axm, hv.y));
+                    // lane 0's west face is the east face of cell -1
+                    const float REl = lane_from_left(fmaf(L1, ax1, c1), e);
                     xw[t] = w.xb_w ? lf : REl;
                     xe0[t] = w.xb_e0 ? c0 : fmaf(L0, ax0, c0);
                     xe1[t] = w.xb_e1 ? c1 : fmaf(L1, ax1, c1);
                 } else {
-                    // west face of cell 128 (lane 63's right neighbour; its
-                    // west neighbour is lane 63's cell 1)
-                    float axp, ayp;
-                    const float Lp = venkat_limit(hv.z, c1, hv.w, hu.z, hd.z, a.eps2, axp, ayp);
-                    const float RWr = lane_from_right(fmaf(-L0, ax0, c0), fmaf(-Lp, axp, hv.z));
+                    // lane 63's east face is the west face of cell 128
+                    const float RWr = lane_from_right(fmaf(-L0, ax0, c0), e);
                     xw[t] = w.xb_w ? c0 : fmaf(-L0, ax0, c0);
                     xe0[t] = w.xb_e0 ? c1 : fmaf(-L1, ax1, c1);
                     xe1[t] = w.xb_e1 ? rt : RWr;
@@ -720,13 +752,12 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
 
 // The ordinate table is read-only for the whole launch: reading it through
 // the constant address space makes it a scalar load, whose wait does not
-// also wait for the next ordinate's window loads.
-using const_ord_ptr = const __attribute__((address_space(4))) OrdConst*;
+// also wait for the next ordinate's window loads (const_ord_ptr).
 
 template <int ORDER, int MODE, typename T, int TY, int W>
 __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
                                                  const float2 (&win)[TY + 4], const float4 (&halo)[TY + kExtraHalo<ORDER>],
-                                                 const float2 (&oldv)[TY], double* facc) {
+                                                 const float2 (&oldv)[TY], const float* edge, double* facc) {
     const const_ord_ptr q = (const_ord_ptr)a.ord + k;
     OrdConst o;
     o.cx = q->cx;
@@ -738,10 +769,10 @@ __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
     o.fx = q->fx;
     o.fy = q->fy;
     switch (o.flags & 3) {
-    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, halo, oldv, facc); break;
-    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, halo, oldv, facc); break;
-    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, halo, oldv, facc); break;
-    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, halo, oldv, facc); break;
+    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, halo, oldv, edge, facc); break;
+    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, halo, oldv, edge, facc); break;
+    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, halo, oldv, edge, facc); break;
+    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, halo, oldv, edge, facc); break;
     }
 }
 
@@ -846,6 +877,11 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
             else if (ahead == 2) wait_vmcnt<R::wait_ahead(2)>();
             else if (ahead == 1) wait_vmcnt<R::wait_ahead(1)>();
             else wait_vmcnt<0>();
+            if (ORDER == 3) {
+                loader_edges<T, TY, W, MODE, XH>(a, k, lds.ring + slot * R::kSlotBytes);
+                // the edge values are in LDS before the compute waves pass the barrier
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            }
             __builtin_amdgcn_s_barrier();
             // the slot of ordinate k - 1 is free now: ordinate k + kSlots - 1 goes there
             const int s_free = slot == 0 ? R::kSlots - 1 : slot - 1;
@@ -990,7 +1026,8 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
             for (int t = 0; t < TY; ++t)
                 oldv[t] = MODE == kAverage ? ring_read<T>(sb + (R::kOldRow0 + wave * TY + t) * R::kRowBytes, lane)
                                            : make_float2(0.0f, 0.0f);
-            process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, halo, oldv, facc);
+            const float* edge = ORDER == 3 ? reinterpret_cast<const float*>(sb + R::kEdgeOffset) + wave * TY : nullptr;
+            process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, halo, oldv, edge, facc);
             slot = slot == R::kSlots - 1 ? 0 : slot + 1;
         }
         if (MODE != kQoiOnly) {
