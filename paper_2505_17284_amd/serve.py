@@ -367,17 +367,22 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
 
 def sweep(n_requests: int = 24, rates=(0.5, 0.9), seed: int = 0, budget_gb: float = 200.0,
           dtypes=("f32", "bf16"), max_instances: int = 64, steps_per_run: int = 32,
-          policies=("deadline", "srpt"), capacity_batched: bool = True, verbose: bool = False):
+          policies=("deadline", "srpt"), capacity_batched: bool = True, verbose: bool = False,
+          capacity: float | None = None):
     """Capacity of both paths (all requests at once), then the one-at-a-time
     path and the continuous-batching loop (each policy) on the same Poisson
-    arrivals at fractions of the one-at-a-time capacity."""
+    arrivals at fractions of the one-at-a-time capacity. `capacity` (solves
+    per second) fixes the rate scale instead of the measured one, so that
+    sweeps split over several runs share it; the back-to-back service times
+    (for the slowdowns) are measured either way."""
     base = I.serving_requests(n_requests, rate=1.0, seed=seed, dtypes=dtypes)
     # capacity: back-to-back service times of the plain path (arrivals all at 0)
     cap_reqs = [(0.0, p) for _, p in base]
     cap_rec, cap_tot = serve_fifo(cap_reqs, verbose=verbose)
     alone = {r["name"]: r["service"] for r in cap_rec}
-    capacity = len(cap_rec) / sum(alone.values())
-    out = dict(requests=n_requests, capacity_solves_per_s=capacity,
+    measured = len(cap_rec) / sum(alone.values())
+    capacity = capacity or measured
+    out = dict(requests=n_requests, capacity_solves_per_s=capacity, measured_capacity_solves_per_s=measured,
                mean_service_s=float(np.mean(list(alone.values()))), policies=list(policies),
                steps_per_run=steps_per_run, rates=[])
     if capacity_batched:
@@ -407,6 +412,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--uq", type=int, default=0, help="run the UQ batch with this many instances")
+    ap.add_argument("--policies", default="deadline,srpt")
+    ap.add_argument("--capacity", type=float, default=0.0, help="rate scale in solves/s (0: measure it)")
+    ap.add_argument("--no-capacity-batched", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args(argv)
     res = {}
@@ -414,7 +422,9 @@ def main(argv=None):
         res["uq"] = uq(args.uq, verbose=args.verbose)
     if args.requests:
         res["serving"] = sweep(args.requests, tuple(float(x) for x in args.rates.split(",")), args.seed,
-                               args.budget_gb, verbose=args.verbose)
+                               args.budget_gb, policies=tuple(args.policies.split(",")),
+                               capacity_batched=not args.no_capacity_batched, verbose=args.verbose,
+                               capacity=args.capacity or None)
     print(json.dumps(res), flush=True)
 
 
