@@ -329,6 +329,8 @@ def main():
                     help="requests per rate of the serving sweep (0 skips it)")
     ap.add_argument("--serving-loads", default="0.5,0.9,1.1",
                     help="arrival rates of the serving sweep as fractions of the one-at-a-time capacity")
+    ap.add_argument("--serving-policies", default="deadline",
+                    help="continuous-batching policies compared with one solve at a time")
     ap.add_argument("--lattice-steps", type=int, default=100,
                     help="Heun steps timed on the 700^2 x 256 lattice (0 skips it)")
     ap.add_argument("--tess-steps", type=int, default=10,
@@ -475,7 +477,8 @@ def main():
     if args.serving_requests:
         loads = tuple(float(x) for x in args.serving_loads.split(","))
         print(f"[bench] serving: {args.serving_requests} requests at loads {loads}", file=sys.stderr, flush=True)
-        line["serving"] = serve.sweep(args.serving_requests, rates=loads, verbose=False)
+        line["serving"] = serve.sweep(args.serving_requests, rates=loads, verbose=False,
+                                      policies=tuple(args.serving_policies.split(",")))
     if not args.no_cpu:
         print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(problem)
