@@ -49,22 +49,25 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload, dtype):
-    """HBM bytes per launch of the Heun stage-2 kernel on `workload` from the
+def measured_traffic(workload, dtype, field="traffic_bytes_per_launch"):
+    """HBM bytes per launch of the Heun stage-2 kernel (`field`
+    traffic_bytes_per_launch_stage1: stage 1) on `workload` from the
     committed rocprofv3 counter summary, or None when the summary is missing
-    or was taken on other sources."""
-    path = os.path.join(PROFILES, f"stage_heun2_{workload}_{dtype}.md")
+    or was taken on other sources. The summary is named for the grid and the
+    ordinate count: stage_heun2_<workload without its stepper suffix>_<dtype>.md."""
+    base = workload[: -len("_heun2")] if workload.endswith("_heun2") else workload
+    path = os.path.join(PROFILES, f"stage_heun2_{base}_{dtype}.md")
     if not os.path.exists(path):
         return None
     fields = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "traffic_bytes_per_launch"):
+            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", field):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    if fields.get("source_sha256") != source_digest() or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != source_digest() or field not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[field])
 
 
 # VALU issue peak without packed FP32 (which this build leaves off): one
@@ -397,10 +400,11 @@ def main():
     stage1_gbs = stage1_bytes / (stage1_ms * 1e-3) / 1e9
     step_bytes = stage1_bytes + bytes_launch
     step_gbs = step_bytes / (secs / args.steps) / 1e9
-    traffic = None
+    traffic = traffic1 = None
     default_shape = not (args.group or args.group_avg or args.rows or args.waves)
     if default_shape:
         traffic = measured_traffic(HEADLINE, args.dtype)
+        traffic1 = measured_traffic(HEADLINE, args.dtype, "traffic_bytes_per_launch_stage1")
     line = {
         "metric": "cell-ordinate updates/s",
         "value": ups,
@@ -433,7 +437,8 @@ def main():
                           "note": "both stages' algorithmic bytes over the wall-clock ms_per_step "
                                   "(finalize launches and gaps included)"},
         "stage1": {"kernel_avg_ms": stage1_ms, "achieved_GBs": stage1_gbs, "frac": stage1_gbs / HBM_PEAK_GBS,
-                   "algorithmic_bytes_per_launch": stage1_bytes},
+                   "algorithmic_bytes_per_launch": stage1_bytes, "traffic": traffic1,
+                   "traffic_over_algorithmic": None if traffic1 is None else traffic1 / stage1_bytes},
         "roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / (step_bytes / problem.cell_ordinates),
     }
     if args.stream_mib:
