@@ -332,16 +332,16 @@ hipError_t launch_stage(int order, int mode, int dtype, int rows, int waves, con
 }
 
 hipError_t launch_stage_batch(int order, int mode, int dtype, int rows, int waves, const BatchLaunch& L, int wgs_per_cu,
-                              int cus, int max_rects, hipStream_t s) {
+                              int cus, int face_lds, hipStream_t s) {
     if (order == 1)
-        return dtype == 0 ? launch_batch_o1_f32(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s)
-                          : launch_batch_o1_bf16(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
+        return dtype == 0 ? launch_batch_o1_f32(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s)
+                          : launch_batch_o1_bf16(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s);
     if (order == 2)
-        return dtype == 0 ? launch_batch_o2_f32(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s)
-                          : launch_batch_o2_bf16(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
+        return dtype == 0 ? launch_batch_o2_f32(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s)
+                          : launch_batch_o2_bf16(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s);
     if (order == 3)
-        return dtype == 0 ? launch_batch_o3_f32(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s)
-                          : launch_batch_o3_bf16(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
+        return dtype == 0 ? launch_batch_o3_f32(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s)
+                          : launch_batch_o3_bf16(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s);
     return hipErrorInvalidValue;
 }
 

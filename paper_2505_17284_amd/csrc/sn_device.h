@@ -29,10 +29,11 @@ constexpr int kGhost = 2;                      // ghost-frame width
 constexpr int kMaxTallies = 8;
 constexpr int kMaxRects = 4;
 constexpr int kMaxProbes = 8;
-// mass, absorption per tally, outflow and inflow per rectangle (summed by the
-// compute waves), then phi, J_x, J_y per space-time probe (by the loader wave)
-constexpr int kMaxQWave = 1 + kMaxTallies + 2 * kMaxRects;
-constexpr int kMaxQ = kMaxQWave + 3 * kMaxProbes;
+// QoI slots: mass and absorption per tally (summed by the compute waves),
+// outflow and inflow per rectangle, then phi, J_x, J_y per space-time probe
+// (both summed by the loader wave)
+constexpr int kMaxQWave = 1 + kMaxTallies;
+constexpr int kMaxQ = kMaxQWave + 2 * kMaxRects + 3 * kMaxProbes;
 constexpr int kMaxFluenceBlocks = 1024;
 constexpr int kProbePerLane = 8;  // probe cells one loader lane accumulates
 // Per-workgroup QoI partials one finalize workgroup sums (256 threads x 8):
@@ -91,8 +92,14 @@ struct StageArgs {
     int32_t n_wg;
     int32_t n_tallies, n_rects, nq;
     int32_t bc[4];
-    int32_t rect[kMaxRects][4];
     float eps2;             // order 3: the limiter's epsilon^2, (h^2)^6
+    // rectangle-boundary faces (outflow and inflow QoIs): the loader wave of
+    // tile t sums every face's flux over the ordinates, its entries held in
+    // registers, or, for tiles with more than kFaceRegs per lane, copied into
+    // dynamic LDS (face_lds bytes: the largest such tile's table; 0 if none)
+    const struct FaceEntry* fent;   // faces, grouped by tile, then by lane
+    const int32_t* ftile;           // [ntiles][3]: first entry, entries per lane, lanes
+    int32_t face_lds;
     // space-time probes: the loader wave of tile t accumulates phi, J_x, J_y
     // of the stage input over the tile's probe cells into QoI slots
     // qprobe + 3 p + m (qprobe = 1 + n_tallies + 2 n_rects)
@@ -101,6 +108,37 @@ struct StageArgs {
     const double* pmom;             // [M][3] w, w xi, w eta in FP64
     int32_t n_probes, qprobe;
 };
+
+// One rectangle-boundary face as a loader lane reads it (16 bytes): element
+// offsets, in a ring slot, of the four cells on the face's normal line, c0
+// c1 | c2 c3 (the face lies between c1 and c2; increasing x for a face
+// normal to x, increasing y otherwise), then, for order 3, of the neighbours
+// of c1 and of c2 across that line (lower, then upper). Offsets take 14 bits;
+// the two high bits of off[0] hold the rectangle, of off[1] the axis (bit
+// 14: y) and the side the rectangle holds (bit 15: c2, i.e. a west or south
+// face), of off[2] first order (bit 14: a face on the grid's boundary) and
+// validity (bit 15; padding entries have it clear).
+struct alignas(16) FaceEntry {
+    uint16_t off[8];
+};
+constexpr uint32_t kFaceOffMask = 0x3fffu;
+constexpr int kFacePerLaneMax = 64;  // entries per loader lane (at most 64 x 64 faces per tile)
+// Entries a loader lane keeps in registers (orders 1 and 2; at order 3 the
+// limiter's operands would raise the kernel's register count); a tile with
+// more per lane reads them from a copy of its table in dynamic LDS.
+constexpr int kFaceRegs = 4;
+constexpr int face_regs(int order) { return order == 3 ? 0 : kFaceRegs; }
+
+// Ring slot layout (the stage kernels' LDS staging, also needed by the
+// host's face tables): the stencil rows of the stage input, 128 cells each,
+// rounded up to whole copies of kWave x 16 bytes; then the x-halo, 4 cells
+// (-2, -1, 128, 129 of the tile) per output row, plus one row above and one
+// below at order 3; then what the stage kind adds. Offsets in elements.
+constexpr int ring_rows_per_copy(int elem_bytes) { return kWave * 16 / (kTileX * elem_bytes); }
+constexpr int ring_halo_elem(int stencil_rows, int elem_bytes) {
+    return (stencil_rows + ring_rows_per_copy(elem_bytes) - 1) / ring_rows_per_copy(elem_bytes) *
+           ring_rows_per_copy(elem_bytes) * kTileX;
+}
 
 // One probe cell as a loader lane reads it: byte offset of the cell in a ring
 // slot, its probe, and its weight (0 for padding).
@@ -202,10 +240,11 @@ hipError_t launch_stage(int order, int mode, int dtype, int rows_per_wave, int w
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // Batched forms. Stage: wgs_per_cu == 0 one workgroup per item, > 0 a
 // persistent grid of that many workgroups per CU, < 0 a persistent grid of the
-// resident capacity; modes kUpdate and kAverage only. Finalize: a persistent
-// grid of `grid`.
+// resident capacity; modes kUpdate and kAverage only; face_lds: the largest
+// face table (StageArgs::face_lds) of the launch's instances. Finalize: a
+// persistent grid of `grid`.
 hipError_t launch_stage_batch(int order, int mode, int dtype, int rows_per_wave, int waves, const BatchLaunch& L,
-                              int wgs_per_cu, int cus, int max_rects, hipStream_t s);
+                              int wgs_per_cu, int cus, int face_lds, hipStream_t s);
 hipError_t launch_finalize_batch(const FinalizeBatch& L, int grid, hipStream_t s);
 hipError_t launch_ghost_fill(int dtype, const GhostArgs& a, hipStream_t s);
 hipError_t launch_phi_init(int dtype, const PhiInitArgs& a, hipStream_t s);
@@ -220,16 +259,16 @@ hipError_t launch_stage_o2_bf16(int mode, int rows, int waves, const StageArgs& 
 hipError_t launch_stage_o3_f32(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_o3_bf16(int mode, int rows, int waves, const StageArgs& a, hipStream_t s);
 hipError_t launch_batch_o1_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s);
+                               int face_lds, hipStream_t s);
 hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s);
+                               int face_lds, hipStream_t s);
 hipError_t launch_batch_o1_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s);
+                               int face_lds, hipStream_t s);
 hipError_t launch_batch_o2_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s);
+                               int face_lds, hipStream_t s);
 hipError_t launch_batch_o3_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s);
+                               int face_lds, hipStream_t s);
 hipError_t launch_batch_o3_bf16(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s);
+                               int face_lds, hipStream_t s);
 
 }  // namespace snk

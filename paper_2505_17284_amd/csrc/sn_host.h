@@ -76,6 +76,11 @@ struct sn_plan {
     std::vector<int32_t> ptile_h;  // [ntiles][3]: first entry, entries per lane, lanes
     std::vector<double> pmom_h;    // [M][3]
     size_t off_pent = 0, off_ptile = 0, off_pmom = 0, off_pacc = 0, off_pstep = 0;
+    // rectangle-boundary faces: the loader waves' per-tile entry tables
+    std::vector<snk::FaceEntry> fent_h;
+    std::vector<int32_t> ftile_h;  // [ntiles][3]: first entry, entries per lane, lanes
+    int face_lds = 0;              // bytes of the largest table read from LDS (more than kFaceRegs per lane)
+    size_t off_fent = 0, off_ftile = 0;
     double source = 0;  // (sum w) h^2 sum_cells Q
     std::vector<snk::OrdConst> ord_h;
     std::vector<snk::RegConst> reg_h;

@@ -29,13 +29,15 @@
 // write boundary cells also write the frame of the new state (write_frame);
 // incoming vacuum/inflow ghosts are constant and set once.
 //
-// Mapping: a wavefront owns 128 consecutive padded columns, two per lane
-// (lanes 1..62 produce output, lanes 0 and 63 are halo; neighbours cross
-// lanes through DPP wave shifts), and TY rows; the four waves of a workgroup
-// are stacked in y and share one LDS copy of each ordinate's rows, halo rows
-// included, while the next ordinate's rows are in flight. Per-cell material
-// data and the incoming scalar flux stay in registers across the ordinate
-// loop. Global accesses are buffer instructions: one scalar resource per
+// Mapping: a compute wave owns 128 consecutive output columns, two per lane
+// (x-neighbours cross lanes through DPP wave shifts; the two cells beyond
+// each end of the tile come from a separately staged x-halo), and TY rows;
+// the W compute waves of a workgroup are stacked in y and share one LDS copy
+// of each ordinate's rows, halo rows included, which a loader wave stages
+// while they compute earlier ordinates. The loader wave also sums the QoIs
+// that need few cells: the currents through rectangle boundaries and the
+// space-time probes. Per-cell material data and the incoming scalar flux
+// stay in registers across the ordinate loop. Global accesses are buffer instructions: one scalar resource per
 // plane, wave-uniform row offsets, one per-lane offset.
 // There is no MFMA: the stage is a bandwidth-bound stencil.
 #pragma once
@@ -49,7 +51,7 @@ namespace snk {
 
 // Stage arguments are read through the constant address space wherever they
 // live (the kernel-argument segment, or a device table of a batched launch):
-// uniform scalar loads, including the indexed rectangle table.
+// uniform scalar loads.
 using SArgs = const __attribute__((address_space(4))) StageArgs&;
 using SArgsPtr = const __attribute__((address_space(4))) StageArgs*;
 
@@ -228,42 +230,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Face-QoI tags of one cell: bit (4 * kind + q) is set when the cell's face of
-// that kind (0 W, 1 E, 2 S, 3 N) lies on the boundary of rectangle q. Each
-// rectangle-boundary face is assigned to the cell inside the rectangle.
-__device__ __forceinline__ uint32_t face_tags(SArgs a, int i, int j, bool valid) {
-    uint32_t tg = 0;
-    if (!valid || j >= a.ny) return 0;
-    for (int q = 0; q < a.n_rects; ++q) {
-        const int i0 = a.rect[q][0], j0 = a.rect[q][1], i1 = a.rect[q][2], j1 = a.rect[q][3];
-        const bool rows = j >= j0 && j < j1, cols = i >= i0 && i < i1;
-        if (rows && i == i0) tg |= 1u << (0 + q);
-        if (rows && i == i1 - 1) tg |= 1u << (4 + q);
-        if (cols && j == j0) tg |= 1u << (8 + q);
-        if (cols && j == j1 - 1) tg |= 1u << (12 + q);
-    }
-    return tg;
-}
-
-// Adds w |Omega.n| trace to the lane's outflow or inflow accumulator of every
-// rectangle whose boundary holds one of the tagged faces. West face: Omega.n =
-// -xi; east: xi; south: -eta; north: eta.
-__device__ __forceinline__ void face_accumulate(uint32_t tg, float tW, float tE, float tS, float tN, double fx,
-                                                double fy, bool sx, bool sy, int n_rects, double* facc,
-                                                int nthreads) {
-#pragma unroll 1
-    while (tg) {
-        const int b = __builtin_ctz(tg);
-        tg &= tg - 1;
-        const int kind = b >> 2, q = b & 3;
-        const float tr = kind == 0 ? tW : (kind == 1 ? tE : (kind == 2 ? tS : tN));
-        const bool out = kind == 0 ? !sx : (kind == 1 ? sx : (kind == 2 ? !sy : sy));
-        const double wgt = kind < 2 ? fx : fy;
-        double* slot = facc + (out ? q : n_rects + q) * nthreads;
-        *slot = fma(wgt, (double)tr, *slot);
-    }
-}
-
 // ---------------------------------------------------------------- per-wave state
 template <int TY>
 struct WaveCtx {
@@ -284,11 +250,9 @@ struct WaveCtx {
     uint32_t planeb;     // bytes per plane
     bool ragged;         // some lane of the wave owns only its first cell (wave-uniform)
     bool v0, v1;         // the lane's cells are output cells of this wave
-    bool any_tag;        // some lane owns a rectangle-boundary face (wave-uniform)
     float2 st[TY];       // dt sigma_t per cell
     float2 bb[TY];       // dt (sigma_s / (2 pi) phi + Q) per cell
     float2 phacc[TY];    // sum_k w_k psi_out over the group's ordinates
-    uint32_t tags[TY];   // face tags, cell 0 in the low half
 };
 
 // ---------------------------------------------------------------- row staging
@@ -303,9 +267,10 @@ struct WaveCtx {
 // full load (several microseconds), not by its bytes: the stages without
 // psi^n rows keep 4 ordinates in flight, the averaging stage, whose slots
 // are almost twice as large, 2, both in ~32 KB of LDS per workgroup, plus
-// 2 n_rects FP64 face accumulators per thread (4 workgroups per compute unit
-// with at most one rectangle, 3 with the lattice's three; measured the same
-// speed).
+// the tile's face table (16 bytes per rectangle-boundary face, a few KB).
+// A slot holds the stencil rows, the x-halo, the order-3 edge traces and the
+// psi^n rows, in that order, so that a cell's offset in it does not depend
+// on the stage kind (the host's face tables hold such offsets).
 #ifndef SN_RING_SLOTS
 #define SN_RING_SLOTS 3
 #endif
@@ -327,8 +292,6 @@ struct Ring {
     static constexpr int kLanesPerRow = kWave / kRowsPerDma;
     static constexpr int kDmaStencil = (kRows + kRowsPerDma - 1) / kRowsPerDma;
     static constexpr int kDmaOld = (kOldRows + kRowsPerDma - 1) / kRowsPerDma;
-    static constexpr int kOldRow0 = kDmaStencil * kRowsPerDma;           // first psi^n row of a slot
-    static constexpr int kSlotRows = kOldRow0 + kDmaOld * kRowsPerDma;
     // x-halo of the output rows (and XH / 2 more rows on each side): cells
     // -2, -1, 128, 129 of the tile, one dword per lane (4 lanes per row for
     // FP32, 2 for BF16)
@@ -337,13 +300,17 @@ struct Ring {
     static constexpr int kHaloLanesPerRow = kHaloRowBytes / 4;
     static constexpr int kHaloRowsPerDma = kWave / kHaloLanesPerRow;
     static constexpr int kDmaHalo = (kHaloRows + kHaloRowsPerDma - 1) / kHaloRowsPerDma;
-    static constexpr int kHaloOffset = kSlotRows * kRowBytes;             // bytes into the slot
+    static constexpr int kHaloOffset = kDmaStencil * kRowsPerDma * kRowBytes;  // bytes into the slot
+    static_assert(kHaloOffset == ring_halo_elem(kRows, (int)sizeof(T)) * (int)sizeof(T),
+                  "slot layout of the host's face tables");
     // Order 3: the loader's trace of the one cell beyond the tile that each
     // output row's x-faces need (east face of cell -1 when xi > 0, west face
     // of cell 128 when xi < 0), one float per output row.
     static constexpr int kEdgeOffset = kHaloOffset + kDmaHalo * kWave * 4;
     static constexpr int kEdgeBytes = XH > 0 ? (W * TY * 4 + 15) / 16 * 16 : 0;
-    static constexpr int kSlotBytes = kEdgeOffset + kEdgeBytes;
+    static constexpr int kOldOffset = kEdgeOffset + kEdgeBytes;          // psi^n rows (averaging stage)
+    static_assert(kOldOffset % 16 == 0, "copies land on 16-byte lanes");
+    static constexpr int kSlotBytes = kOldOffset + kDmaOld * kRowsPerDma * kRowBytes;
     static constexpr int kDmaPerOrd = kDmaStencil + kDmaOld + kDmaHalo;  // copies per ordinate
     static constexpr int kBytes = kSlots * kSlotBytes;
     // outstanding copies allowed while waiting for the oldest ordinate when
@@ -427,7 +394,7 @@ __device__ __forceinline__ void ring_issue(SArgs a, int k, int yw, const LoaderO
 #pragma unroll
         for (int i = 0; i < R::kDmaOld; ++i)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                ro, (lds_ptr)(slot + (R::kOldRow0 + i * R::kRowsPerDma) * R::kRowBytes), R::kDmaBytes, lo.old,
+                ro, (lds_ptr)(slot + R::kOldOffset + i * R::kRowsPerDma * R::kRowBytes), R::kDmaBytes, lo.old,
                 (uint32_t)(yw + kGhost + i * R::kRowsPerDma) * pitchb, 0, SN_OLD_CPOL);
     }
 }
@@ -490,6 +457,89 @@ __device__ __forceinline__ void loader_edges(SArgs a, int k, char* slot) {
         }
         reinterpret_cast<float*>(slot + R::kEdgeOffset)[q] = e;
     }
+}
+
+// A staged cell of a ring slot by its element offset (face tables).
+template <typename T>
+__device__ __forceinline__ float slot_cell(const char* sb, uint32_t o) {
+    o &= kFaceOffMask;
+    if (sizeof(T) == 4) return *reinterpret_cast<const float*>(sb + 4 * o);
+    return bf16_widen(*reinterpret_cast<const uint16_t*>(sb + 2 * o));
+}
+
+// Rectangle-boundary faces (outflow and inflow QoIs of Sec. 3.1.2), in the
+// loader wave once ordinate k's rows are in slot `sb`: every face of the
+// lane's table entries (all of one rectangle) adds w |Omega.n| times the
+// face's upwind trace to the lane's outflow or inflow sum in FP64. The trace
+// is reconstructed from the staged cells as the compute waves reconstruct
+// it for the flux: the upwind cell (order 1), plus half its minmod slope
+// along the normal (order 2), plus its Venkatakrishnan-limited gradient
+// (order 3; first order on the grid's boundary). One lane per face instead
+// of a 64-lane pass of every compute wave that owns one.
+struct FaceOrd {
+    bool sx, sy;    // xi > 0, eta > 0
+    double fx, fy;  // w |xi|, w |eta|
+};
+
+template <int ORDER, typename T>
+__device__ __forceinline__ void face_flux(const FaceOrd& fo, float eps2, const char* sb, uint4 raw, double& fout,
+                                          double& fin) {
+    const uint32_t o0 = raw.x & 0xffffu, o1 = raw.x >> 16, o2 = raw.y & 0xffffu, o3 = raw.y >> 16;
+    const bool yaxis = (o1 >> 14) & 1u, holds_c2 = (o1 >> 15) & 1u;
+    const bool first = (o2 >> 14) & 1u, valid = (o2 >> 15) & 1u;
+    const bool dir = yaxis ? fo.sy : fo.sx;  // the flow crosses the face from c1 to c2
+    const float c1 = slot_cell<T>(sb, o1), c2 = slot_cell<T>(sb, o2);
+    float tr;
+    if (ORDER == 1) {
+        tr = dir ? c1 : c2;
+    } else if (ORDER == 2) {
+        const float c0 = slot_cell<T>(sb, o0), c3 = slot_cell<T>(sb, o3);
+        const float d12 = c2 - c1;
+        tr = dir ? fmaf(0.5f, minmod(c1 - c0, d12), c1) : fmaf(-0.5f, minmod(d12, c3 - c2), c2);
+    } else {
+        const float c0 = slot_cell<T>(sb, o0), c3 = slot_cell<T>(sb, o3);
+        const float t1m = slot_cell<T>(sb, raw.z & 0xffffu), t1p = slot_cell<T>(sb, raw.z >> 16);
+        const float t2m = slot_cell<T>(sb, raw.w & 0xffffu), t2p = slot_cell<T>(sb, raw.w >> 16);
+        const float c = dir ? c1 : c2;                          // upwind cell
+        const float nm = dir ? c0 : c1, np = dir ? c2 : c3;      // its neighbours along the normal
+        const float tm = dir ? t1m : t2m, tp = dir ? t1p : t2p;  // and across it
+        float gx, gy;
+        const float L = venkat_limit(c, yaxis ? tm : nm, yaxis ? tp : np, yaxis ? nm : tm, yaxis ? np : tp, eps2,
+                                     gx, gy);
+        tr = first ? c : fmaf(dir ? L : -L, yaxis ? gy : gx, c);
+    }
+    const bool out = dir != holds_c2;
+    const double r = fma(yaxis ? fo.fy : fo.fx, (double)tr, out ? fout : fin);
+    if (valid) {
+        if (out) fout = r;
+        else fin = r;
+    }
+}
+
+template <int ORDER, typename T>
+__device__ __forceinline__ FaceOrd face_ord(SArgs a, int k) {
+    const const_ord_ptr ok = (const_ord_ptr)a.ord + k;  // scalar loads
+    const int fg = ok->flags;
+    return FaceOrd{(fg & 1) != 0, (fg & 2) != 0, ok->fx, ok->fy};
+}
+
+// N entries held in registers (the common case: every load of the ordinate
+// in flight together).
+template <int ORDER, typename T, int N>
+__device__ __forceinline__ void face_fluxes_regs(SArgs a, int k, const char* sb, const uint4 (&fr)[kFaceRegs],
+                                                 double& fout, double& fin) {
+    const FaceOrd fo = face_ord<ORDER, T>(a, k);
+#pragma unroll
+    for (int e = 0; e < N; ++e) face_flux<ORDER, T>(fo, a.eps2, sb, fr[e], fout, fin);
+}
+
+// fl entries from the tile's table in LDS (tiles with more faces per lane).
+template <int ORDER, typename T>
+__device__ __forceinline__ void face_fluxes_lds(SArgs a, int k, const char* sb, const FaceEntry* tab, int fl,
+                                                double& fout, double& fin) {
+    const FaceOrd fo = face_ord<ORDER, T>(a, k);
+    for (int e = 0; e < fl; ++e)
+        face_flux<ORDER, T>(fo, a.eps2, sb, *reinterpret_cast<const uint4*>(tab + e), fout, fin);
 }
 
 // Stores one cell pair (or the first cell only) at byte offset `off` of plane base `p`.
@@ -583,7 +633,7 @@ __device__ __forceinline__ void write_frame_all(SArgs a, const OrdConst& o, int 
 template <int ORDER, int MODE, typename T, int TY, int W, bool SX, bool SY>
 __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k, WaveCtx<TY>& w,
                                                const float2 (&win)[TY + 4], const float4 (&halo)[TY + kExtraHalo<ORDER>],
-                                               const float2 (&oldv)[TY], const float* edge, double* facc) {
+                                               const float2 (&oldv)[TY], const float* edge) {
     constexpr int D = SY ? 0 : 1;  // y-traces of output row t: Ry[t + 1 + D] (south), Ry[t + 2 + D] (north)
     constexpr float HX = SX ? 0.5f : -0.5f;
     constexpr float HY = SY ? 0.5f : -0.5f;
@@ -739,14 +789,6 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
             w.phacc[t].x = fmaf(o.w, v.x, w.phacc[t].x);
             w.phacc[t].y = fmaf(o.w, v.y, w.phacc[t].y);
         }
-
-        if (w.any_tag) {  // wave-uniform: some lane owns a rectangle-boundary face
-            const uint32_t tg = w.tags[t];
-            if (tg & 0xffffu)
-                face_accumulate(tg & 0xffffu, tW0, tE0, tS.x, tN.x, o.fx, o.fy, SX, SY, a.n_rects, facc, kWave * W);
-            if (tg >> 16)
-                face_accumulate(tg >> 16, tE0, tE1, tS.y, tN.y, o.fx, o.fy, SX, SY, a.n_rects, facc, kWave * W);
-        }
     }
 }
 
@@ -757,7 +799,7 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
 template <int ORDER, int MODE, typename T, int TY, int W>
 __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
                                                  const float2 (&win)[TY + 4], const float4 (&halo)[TY + kExtraHalo<ORDER>],
-                                                 const float2 (&oldv)[TY], const float* edge, double* facc) {
+                                                 const float2 (&oldv)[TY], const float* edge) {
     const const_ord_ptr q = (const_ord_ptr)a.ord + k;
     OrdConst o;
     o.cx = q->cx;
@@ -769,10 +811,10 @@ __device__ __forceinline__ void process_ordinate(SArgs a, int k, WaveCtx<TY>& w,
     o.fx = q->fx;
     o.fy = q->fy;
     switch (o.flags & 3) {
-    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, halo, oldv, edge, facc); break;
-    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, halo, oldv, edge, facc); break;
-    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, halo, oldv, edge, facc); break;
-    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, halo, oldv, edge, facc); break;
+    case 3: stage_ordinate<ORDER, MODE, T, TY, W, true, true>(a, o, k, w, win, halo, oldv, edge); break;
+    case 2: stage_ordinate<ORDER, MODE, T, TY, W, false, true>(a, o, k, w, win, halo, oldv, edge); break;
+    case 1: stage_ordinate<ORDER, MODE, T, TY, W, true, false>(a, o, k, w, win, halo, oldv, edge); break;
+    default: stage_ordinate<ORDER, MODE, T, TY, W, false, false>(a, o, k, w, win, halo, oldv, edge); break;
     }
 }
 
@@ -794,6 +836,7 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nwg) {
 template <typename T, int TY, int W, int MODE, int XH>
 struct StageLds {
     double red[W][kMaxQWave];
+    double face_red[2 * kMaxRects];   // the loader wave's outflow, then inflow, per rectangle
     double probe_red[kMaxProbes][3];  // the loader wave's probe moments
     alignas(16) char ring[Ring<T, TY, W, MODE, XH>::kBytes];
 };
@@ -802,10 +845,10 @@ using const_f64_ptr = const __attribute__((address_space(4))) double*;
 using const_i32_ptr = const __attribute__((address_space(4))) int32_t*;
 
 // The work of logical workgroup `logical` of one stage launch: tile and
-// ordinate group, all ordinates of the group, epilogues. facc_all holds
-// 2 n_rects FP64 accumulators per thread.
+// ordinate group, all ordinates of the group, epilogues. ftab: the dynamic
+// LDS that holds the tile's face table (a.face_lds bytes).
 template <int ORDER, int MODE, typename T, int TY, int W>
-__device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_all,
+__device__ __forceinline__ void stage_tile(SArgs a, int logical, FaceEntry* ftab,
                                            StageLds<T, TY, W, MODE, kExtraHalo<ORDER>>& lds) {
     constexpr int XH = kExtraHalo<ORDER>;
     using R = Ring<T, TY, W, MODE, XH>;
@@ -843,6 +886,30 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         for (int e = 0; e < kProbePerLane; ++e) {
             poff[e] = 0;
             pwt[e] = 0.0;
+        }
+        // Rectangle-boundary faces: fl entries per lane, flanes lanes, a
+        // lane's entries of one rectangle fq; up to kFaceRegs entries in
+        // registers, more from a copy of the tile's table in LDS. Loaded
+        // before any copy is in flight.
+        int fl = 0, flanes = 0, fq = -1;
+        double fout = 0.0, fin = 0.0;
+        uint4 fr[kFaceRegs];
+#pragma unroll
+        for (int e = 0; e < kFaceRegs; ++e) fr[e] = make_uint4(0u, 0u, 0u, 0u);
+        if (a.n_rects > 0) {
+            const const_i32_ptr ft = (const_i32_ptr)a.ftile + 3 * tile;
+            const int fb = ft[0];
+            fl = ft[1];
+            flanes = ft[2];
+            const uint4* src = reinterpret_cast<const uint4*>(a.fent + fb);
+            if (fl > face_regs(ORDER)) {
+                for (int e = lane; e < fl * flanes; e += kWave) ftab[e] = a.fent[fb + e];
+            } else if (lane < flanes) {
+#pragma unroll
+                for (int e = 0; e < kFaceRegs; ++e)
+                    if (e < fl) fr[e] = src[lane * fl + e];
+            }
+            if (lane < flanes) fq = (int)(a.fent[fb + lane * fl].off[0] >> 14);
         }
         if (a.n_probes > 0) {
             const const_i32_ptr pt = (const_i32_ptr)a.ptile + 3 * tile;
@@ -907,7 +974,28 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
                 pm1 = fma(w1, v, pm1);
                 pm2 = fma(w2, v, pm2);
             }
+            if (fl > 0 && lane < flanes) {  // fl: workgroup-uniform
+                const char* sb = lds.ring + slot * R::kSlotBytes;
+                if (fl > face_regs(ORDER)) {
+                    face_fluxes_lds<ORDER, T>(a, k, sb, ftab + lane * fl, fl, fout, fin);
+                } else {
+                    switch (fl) {
+                    case 1: face_fluxes_regs<ORDER, T, 1>(a, k, sb, fr, fout, fin); break;
+                    case 2: face_fluxes_regs<ORDER, T, 2>(a, k, sb, fr, fout, fin); break;
+                    case 3: face_fluxes_regs<ORDER, T, 3>(a, k, sb, fr, fout, fin); break;
+                    default: face_fluxes_regs<ORDER, T, 4>(a, k, sb, fr, fout, fin); break;
+                    }
+                }
+            }
             slot = slot == R::kSlots - 1 ? 0 : slot + 1;
+        }
+        for (int q = 0; q < a.n_rects; ++q) {  // per rectangle, the wave's sums in lane order
+            const double vo = wave_sum(fq == q ? fout : 0.0);
+            const double vi = wave_sum(fq == q ? fin : 0.0);
+            if (lane == 0) {
+                lds.face_red[q] = vo;
+                lds.face_red[a.n_rects + q] = vi;
+            }
         }
         if (a.n_probes > 0) {  // per probe, the wave's sum in lane order
             for (int p = 0; p < a.n_probes; ++p) {
@@ -956,8 +1044,6 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
                                             (w.y0 <= a.ny - 1 && a.ny - 1 < w.y0 + TY));
     }
     const int ny = a.ny;
-    double* facc = facc_all + tid;
-    for (int s = 0; s < 2 * a.n_rects; ++s) facc[s * kWave * W] = 0.0;
 
     // Per-cell constants of the stage; mass and absorption of the stage input
     // (group-0 workgroups only).
@@ -999,15 +1085,8 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
         }
     }
 
-    uint32_t my_tags = 0;
 #pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        const int j = w.y0 + t;
-        w.tags[t] = face_tags(a, w.i0, j, w.v0) | (face_tags(a, w.i0 + 1, j, w.v1) << 16);
-        my_tags |= w.tags[t];
-        w.phacc[t] = make_float2(0.0f, 0.0f);
-    }
-    w.any_tag = __any(my_tags != 0);
+    for (int t = 0; t < TY; ++t) w.phacc[t] = make_float2(0.0f, 0.0f);
 
     {
         __syncthreads();  // set-up done; the loader's first copies are in flight
@@ -1024,10 +1103,10 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
                 halo[t] = halo_read<T>(sb + R::kHaloOffset + (wave * TY + t) * R::kHaloRowBytes);
 #pragma unroll
             for (int t = 0; t < TY; ++t)
-                oldv[t] = MODE == kAverage ? ring_read<T>(sb + (R::kOldRow0 + wave * TY + t) * R::kRowBytes, lane)
+                oldv[t] = MODE == kAverage ? ring_read<T>(sb + R::kOldOffset + (wave * TY + t) * R::kRowBytes, lane)
                                            : make_float2(0.0f, 0.0f);
             const float* edge = ORDER == 3 ? reinterpret_cast<const float*>(sb + R::kEdgeOffset) + wave * TY : nullptr;
-            process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, halo, oldv, edge, facc);
+            process_ordinate<ORDER, MODE, T, TY, W>(a, k, w, win, halo, oldv, edge);
             slot = slot == R::kSlots - 1 ? 0 : slot + 1;
         }
         if (MODE != kQoiOnly) {
@@ -1044,16 +1123,13 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
     }
 
     // Workgroup reduction of the QoI partial sums, fixed order.
-    const int nt = a.n_tallies, nr = a.n_rects;
-    for (int s = 0; s < 2 * nr; ++s) {
-        const double v = wave_sum(facc[s * kWave * W]);
-        if (lane == 0) red[wave][1 + nt + s] = v;
-    }
     __syncthreads();
     if (tid < a.nq) {
         double tot;
         if (tid >= a.qprobe) {  // a probe moment, from the loader wave
             tot = lds.probe_red[(tid - a.qprobe) / 3][(tid - a.qprobe) % 3];
+        } else if (tid > a.n_tallies) {  // a face current, from the loader wave
+            tot = lds.face_red[tid - 1 - a.n_tallies];
         } else {
             tot = red[0][tid];
 #pragma unroll
@@ -1067,7 +1143,7 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, double* facc_al
 // Workgroup: W compute waves + 1 loader wave.
 template <int ORDER, int MODE, typename T, int TY, int W>
 __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_kernel(const StageArgs a) {
-    extern __shared__ double facc_all[];  // [2 n_rects][kWave W] per-thread FP64 face accumulators
+    extern __shared__ FaceEntry ftab[];  // the tile's face table (a.face_lds bytes)
     __shared__ StageLds<T, TY, W, MODE, kExtraHalo<ORDER>> lds;
     // The averaging stage runs its logical workgroups in reverse: it reads
     // psi^(1), which the update stage just wrote in forward order, so it
@@ -1076,7 +1152,7 @@ __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_kernel(const StageAr
     // reads first, written last (700^2 x 256 lattice, FP32: 0.609 -> 0.601
     // ms per Heun step; 1300^2 x 512 cavity: 3.73 -> 3.69 ms).
     const int l = xcd_contiguous(blockIdx.x, gridDim.x);
-    stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, MODE == kAverage ? (int)gridDim.x - 1 - l : l, facc_all, lds);
+    stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)&a, MODE == kAverage ? (int)gridDim.x - 1 - l : l, ftab, lds);
 }
 
 // The selected instance j holding item (first[j] <= item < first[j + 1]):
@@ -1121,7 +1197,7 @@ __device__ __forceinline__ InstanceRef find_instance(const int32_t* first, const
 // the concatenated workgroup lists of the selected instances.
 template <int ORDER, int MODE, typename T, int TY, int W>
 __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_batch_kernel(const BatchLaunch L) {
-    extern __shared__ double facc_all[];
+    extern __shared__ FaceEntry ftab[];  // the largest face table of the launch's instances
     __shared__ StageLds<T, TY, W, MODE, kExtraHalo<ORDER>> lds;
     __shared__ int inst[2];
     const int pos = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -1129,17 +1205,17 @@ __global__ void __launch_bounds__(kWave * (W + 1)) sn_stage_batch_kernel(const B
         const int item = base + pos;
         if (item >= L.total) break;  // workgroup-uniform; later rounds are past the end too
         const InstanceRef r = find_instance(L.first, L.sel, L.n_sel, item, inst);
-        stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)(L.args + r.sel), item - r.first, facc_all, lds);
+        stage_tile<ORDER, MODE, T, TY, W>(*(SArgsPtr)(L.args + r.sel), item - r.first, ftab, lds);
     }
 }
 
 template <int ORDER, int MODE, typename T, int TY>
 static void launch_w(int waves, const StageArgs& a, hipStream_t s) {
-    const size_t lds_per_thread = (size_t)2 * a.n_rects * sizeof(double);
+    const size_t lds = (size_t)a.face_lds;
     if (waves == 4)
-        hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 4>), dim3(a.n_wg), dim3(kWave * 5), lds_per_thread * kWave * 4, s, a);
+        hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 4>), dim3(a.n_wg), dim3(kWave * 5), lds, s, a);
     else
-        hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 8>), dim3(a.n_wg), dim3(kWave * 9), lds_per_thread * kWave * 8, s, a);
+        hipLaunchKernelGGL((sn_stage_kernel<ORDER, MODE, T, TY, 8>), dim3(a.n_wg), dim3(kWave * 9), lds, s, a);
 }
 
 template <int ORDER, typename T>
@@ -1178,33 +1254,40 @@ static int batch_grid(K kernel, int threads, size_t lds, int total, int wgs_per_
     return (int)(g < total ? g : (total > 0 ? total : 1));
 }
 
+// Face tables take at most kFacePerLaneMax x kWave entries; the batched
+// launch reserves the largest of its instances', rounded up to 4 KB steps
+// (one residency figure cached per step).
+constexpr int kFaceLdsStep = 4096;
+constexpr int kFaceLdsSteps = kFacePerLaneMax * kWave * (int)sizeof(FaceEntry) / kFaceLdsStep;
+
 template <int ORDER, int MODE, typename T, int TY, int W>
-static void launch_batch_shape(const BatchLaunch& L, int wgs_per_cu, int cus, int max_rects, hipStream_t s) {
-    static int resident[kMaxRects + 1] = {};  // per face-accumulator size, filled on first use
-    const size_t lds = (size_t)2 * max_rects * sizeof(double) * kWave * W;
+static void launch_batch_shape(const BatchLaunch& L, int wgs_per_cu, int cus, int face_lds, hipStream_t s) {
+    static int resident[kFaceLdsSteps + 1] = {};  // per face-table size step, filled on first use
+    const int step = (face_lds + kFaceLdsStep - 1) / kFaceLdsStep;
+    const size_t lds = (size_t)step * kFaceLdsStep;
     auto kern = sn_stage_batch_kernel<ORDER, MODE, T, TY, W>;
-    const int grid = batch_grid(kern, kWave * (W + 1), lds, L.total, wgs_per_cu, cus, &resident[max_rects]);
+    const int grid = batch_grid(kern, kWave * (W + 1), lds, L.total, wgs_per_cu, cus, &resident[step]);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * (W + 1)), lds, s, L);
 }
 
 template <int ORDER, int MODE, typename T, int TY>
-static void launch_batch_w(int waves, const BatchLaunch& L, int wgs_per_cu, int cus, int max_rects, hipStream_t s) {
-    if (waves == 4) launch_batch_shape<ORDER, MODE, T, TY, 4>(L, wgs_per_cu, cus, max_rects, s);
-    else launch_batch_shape<ORDER, MODE, T, TY, 8>(L, wgs_per_cu, cus, max_rects, s);
+static void launch_batch_w(int waves, const BatchLaunch& L, int wgs_per_cu, int cus, int face_lds, hipStream_t s) {
+    if (waves == 4) launch_batch_shape<ORDER, MODE, T, TY, 4>(L, wgs_per_cu, cus, face_lds, s);
+    else launch_batch_shape<ORDER, MODE, T, TY, 8>(L, wgs_per_cu, cus, face_lds, s);
 }
 
 template <int ORDER, typename T>
 static hipError_t launch_batch_tu(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                                  int max_rects, hipStream_t s) {
+                                  int face_lds, hipStream_t s) {
     if (waves != 4 && waves != 8) return hipErrorInvalidValue;
     if (mode != kUpdate && mode != kAverage) return hipErrorInvalidValue;
-    if (max_rects < 0 || max_rects > kMaxRects) return hipErrorInvalidValue;
+    if (face_lds < 0 || face_lds > kFaceLdsSteps * kFaceLdsStep) return hipErrorInvalidValue;
     if (rows == 2) {
-        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 2>(waves, L, wgs_per_cu, cus, max_rects, s);
-        else launch_batch_w<ORDER, kAverage, T, 2>(waves, L, wgs_per_cu, cus, max_rects, s);
+        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 2>(waves, L, wgs_per_cu, cus, face_lds, s);
+        else launch_batch_w<ORDER, kAverage, T, 2>(waves, L, wgs_per_cu, cus, face_lds, s);
     } else if (rows == 4) {
-        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 4>(waves, L, wgs_per_cu, cus, max_rects, s);
-        else launch_batch_w<ORDER, kAverage, T, 4>(waves, L, wgs_per_cu, cus, max_rects, s);
+        if (mode == kUpdate) launch_batch_w<ORDER, kUpdate, T, 4>(waves, L, wgs_per_cu, cus, face_lds, s);
+        else launch_batch_w<ORDER, kAverage, T, 4>(waves, L, wgs_per_cu, cus, face_lds, s);
     } else {
         return hipErrorInvalidValue;
     }

@@ -8,8 +8,8 @@ hipError_t launch_stage_o2_f32(int mode, int rows, int waves, const StageArgs& a
 }
 
 hipError_t launch_batch_o2_f32(int mode, int rows, int waves, const BatchLaunch& L, int wgs_per_cu, int cus,
-                               int max_rects, hipStream_t s) {
-    return launch_batch_tu<2, float>(mode, rows, waves, L, wgs_per_cu, cus, max_rects, s);
+                               int face_lds, hipStream_t s) {
+    return launch_batch_tu<2, float>(mode, rows, waves, L, wgs_per_cu, cus, face_lds, s);
 }
 
 }  // namespace snk

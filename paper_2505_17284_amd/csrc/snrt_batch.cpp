@@ -233,7 +233,7 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     // stage of every member is one launch (plus one finalize), members
     // dropping out as they finish.
     std::vector<int64_t> left(n_slots, 0);
-    int max_rects = 0;
+    int face_lds = 0;  // the largest face table of the run's plans
     std::vector<std::vector<int>> groups;
     {
         std::vector<int> big;
@@ -247,7 +247,7 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             if (B->quota[i] > 0) left[i] = std::min<int64_t>(left[i], B->quota[i]);
             if (B->quota[i] == SN_STEPS_PAUSED) left[i] = 0;
             if (left[i] == 0) continue;
-            max_rects = std::max(max_rects, B->slot[i]->n_rects);
+            face_lds = std::max(face_lds, B->slot[i]->face_lds);
             const uint64_t f = 2 * (uint64_t)B->slot[i]->psi_bytes;
             if (cap == 0 || f > cap) {
                 big.push_back(i);
@@ -339,7 +339,7 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
             bl.n_sel = r.n;
             bl.total = r.total;
             HIP_TRY(launch_stage_batch(B->o.order, r.mode, B->o.psi_dtype, B->o.rows_per_wave, B->o.waves_per_group,
-                                       bl, B->o.workgroups_per_cu, B->cus, max_rects, q),
+                                       bl, B->o.workgroups_per_cu, B->cus, face_lds, q),
                     "batched stage launch");
             FinalizeBatch fb{};
             fb.args = reinterpret_cast<const FinalizeArgs*>(B->ws + B->off_final);
@@ -358,7 +358,7 @@ sn_status sn_batch_run(sn_batch* B, int32_t n_steps, void* stream) {
     if (B->o.use_graph) {
         key.reserve(host.size() + 5 * recs.size() + 2);
         key.push_back((int32_t)recs.size());
-        key.push_back(max_rects);
+        key.push_back(face_lds);
         for (const Rec& r : recs) {
             key.push_back((int32_t)r.off);
             key.push_back(r.n);

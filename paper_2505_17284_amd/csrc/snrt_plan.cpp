@@ -301,6 +301,116 @@ sn_status probe_tables(sn_plan* P) {
     return SN_OK;
 }
 
+// The stage kernels' loader wave sums the outflow and inflow through the
+// rectangles' boundaries (Sec. 3.1.2, R11): each boundary face of a
+// rectangle is assigned to the cell inside it, so to that cell's tile. Per
+// tile: the faces grouped by rectangle (west, east, south, north faces, in
+// cell order), dealt fl to a lane, a lane's faces all of one rectangle (the
+// last lane of a rectangle padded), fl the smallest that fits the tile's
+// faces into one wave. An entry holds the ring-slot offsets of the cells the
+// face's trace is reconstructed from (FaceEntry); every such cell is staged
+// with the tile: the line c0..c3 lies in the face's row or column within
+// two cells of the tile, and at order 3 the cells across it lie in the rows
+// next to an output row, whose x-halo is staged too.
+sn_status face_tables(sn_plan* P) {
+    const int ntiles = P->ntx * P->nty;
+    const int tile_rows = P->waves * P->rows;
+    const int xh = P->order == 3 ? 1 : 0;  // x-halo rows staged above and below the output rows
+    const int halo0 = ring_halo_elem(tile_rows + 4, (int)P->elem);
+    P->ftile_h.assign((size_t)3 * ntiles, 0);
+    P->fent_h.clear();
+    P->face_lds = 0;
+    if (P->n_rects == 0) return SN_OK;
+
+    struct Face {
+        int tile, q;
+        FaceEntry e;
+    };
+    std::vector<Face> faces;
+    bool staged = true;
+    // element offset in the slot of tile (tx, ty) of grid cell (i, j), ghost cells included
+    auto off = [&](int tx, int ty, int i, int j) -> uint16_t {
+        const int c = i - tx * kTileX, r = j - ty * tile_rows + kGhost;
+        int o = -1;
+        if (c >= 0 && c < kTileX) {
+            if (r >= 0 && r < tile_rows + 4) o = r * kTileX + c;
+        } else if (c >= -2 && c < kTileX + 2) {
+            const int hr = r - kGhost + xh;
+            if (hr >= 0 && hr < tile_rows + 2 * xh) o = halo0 + hr * 4 + (c < 0 ? c + 2 : c - kTileX + 2);
+        }
+        if (o < 0 || o > (int)kFaceOffMask) {
+            staged = false;
+            return 0;
+        }
+        return (uint16_t)o;
+    };
+    // face between cells (i1c, j1c) and (i2c, j2c) = (i1c, j1c) + d, d the unit step along the axis
+    auto add = [&](int q, int iin, int jin, bool yaxis, bool holds_c2, int i1c, int j1c, bool first) {
+        const int tx = iin / kTileX, ty = jin / tile_rows;
+        const int dx = yaxis ? 0 : 1, dy = yaxis ? 1 : 0;  // along the normal
+        const int ex = yaxis ? 1 : 0, ey = yaxis ? 0 : 1;  // across it
+        FaceEntry e{};
+        e.off[0] = off(tx, ty, i1c - dx, j1c - dy);
+        e.off[1] = off(tx, ty, i1c, j1c);
+        e.off[2] = off(tx, ty, i1c + dx, j1c + dy);
+        e.off[3] = off(tx, ty, i1c + 2 * dx, j1c + 2 * dy);
+        if (P->order == 3) {
+            e.off[4] = off(tx, ty, i1c - ex, j1c - ey);
+            e.off[5] = off(tx, ty, i1c + ex, j1c + ey);
+            e.off[6] = off(tx, ty, i1c + dx - ex, j1c + dy - ey);
+            e.off[7] = off(tx, ty, i1c + dx + ex, j1c + dy + ey);
+        }
+        e.off[0] |= (uint16_t)(q << 14);
+        e.off[1] |= (uint16_t)((yaxis ? 1 : 0) << 14 | (holds_c2 ? 1 : 0) << 15);
+        e.off[2] |= (uint16_t)((first ? 1 : 0) << 14 | 1 << 15);
+        faces.push_back(Face{ty * P->ntx + tx, q, e});
+    };
+    for (int q = 0; q < P->n_rects; ++q) {
+        const int i0 = P->rects[q][0], j0 = P->rects[q][1], i1 = P->rects[q][2], j1 = P->rects[q][3];
+        for (int j = j0; j < j1; ++j) add(q, i0, j, false, true, i0 - 1, j, i0 == 0);             // west
+        for (int j = j0; j < j1; ++j) add(q, i1 - 1, j, false, false, i1 - 1, j, i1 == P->nx);    // east
+        for (int i = i0; i < i1; ++i) add(q, i, j0, true, true, i, j0 - 1, j0 == 0);              // south
+        for (int i = i0; i < i1; ++i) add(q, i, j1 - 1, true, false, i, j1 - 1, j1 == P->ny);     // north
+    }
+    if (!staged) return fail(SN_ERR_UNSUPPORTED, "a rectangle face reads a cell its tile does not stage");
+    std::stable_sort(faces.begin(), faces.end(), [](const Face& x, const Face& y) {
+        return x.tile != y.tile ? x.tile < y.tile : x.q < y.q;
+    });
+    for (size_t b = 0; b < faces.size();) {
+        const int tile = faces[b].tile;
+        size_t e = b;
+        int cnt[kMaxRects] = {};
+        while (e < faces.size() && faces[e].tile == tile) cnt[faces[e++].q]++;
+        int fl = 0, lanes = 0;
+        for (int cand = 1; cand <= kFacePerLaneMax && fl == 0; ++cand) {
+            int l = 0;
+            for (int q = 0; q < P->n_rects; ++q) l += (cnt[q] + cand - 1) / cand;
+            if (l <= kWave) {
+                fl = cand;
+                lanes = l;
+            }
+        }
+        if (fl == 0)  // a tile holds at most 4 x (2 x 128 + 2 x 8 x 4) faces
+            return fail(SN_ERR_UNSUPPORTED, "%zu rectangle faces in one tile", e - b);
+        P->ftile_h[3 * tile] = (int32_t)P->fent_h.size();
+        P->ftile_h[3 * tile + 1] = fl;
+        P->ftile_h[3 * tile + 2] = lanes;
+        for (size_t c = b; c < e;) {  // one rectangle's faces
+            const int q = faces[c].q;
+            int m = 0;
+            for (; c < e && faces[c].q == q; ++c, ++m) P->fent_h.push_back(faces[c].e);
+            for (; m % fl != 0; ++m) {
+                FaceEntry pad{};
+                pad.off[0] = (uint16_t)(q << 14);
+                P->fent_h.push_back(pad);
+            }
+        }
+        if (fl > face_regs(P->order)) P->face_lds = std::max(P->face_lds, fl * lanes * (int)sizeof(FaceEntry));
+        b = e;
+    }
+    return SN_OK;
+}
+
 sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int waves) {
     // dt = CFL * h (Sec. 5.1.3), adjusted so that N_t dt = T (Sec. 4.3).
     const double r = P->t_end / (P->cfl * P->h);
@@ -344,6 +454,8 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
     {
         const sn_status st = probe_tables(P);
         if (st != SN_OK) return st;
+        const sn_status sf = face_tables(P);
+        if (sf != SN_OK) return sf;
     }
 
     P->psi_bytes = align256((size_t)P->M * (size_t)P->plane * P->elem);
@@ -396,6 +508,13 @@ sn_status derive(sn_plan* P, int group_size, int group_size_avg, int rows, int w
         off += align256((size_t)P->n_windows * P->n_probes * 3 * sizeof(double));
         P->off_pstep = off;
         off += align256((size_t)3 * P->n_probes * sizeof(int32_t));
+    }
+    P->off_fent = off;
+    P->off_ftile = off;
+    if (P->n_rects > 0) {
+        off += align256(std::max<size_t>(1, P->fent_h.size()) * sizeof(FaceEntry));
+        P->off_ftile = off;
+        off += align256(P->ftile_h.size() * sizeof(int32_t));
     }
     P->scratch_bytes = off;
 
@@ -474,8 +593,11 @@ StageArgs snh::stage_args(const sn_plan* P, const char* in, const char* old, cha
     a.n_rects = P->n_rects;
     a.nq = P->nq;
     for (int s = 0; s < 4; ++s) a.bc[s] = P->bc[s];
-    for (int r = 0; r < P->n_rects; ++r)
-        for (int e = 0; e < 4; ++e) a.rect[r][e] = P->rects[r][e];
+    if (P->n_rects > 0) {
+        a.fent = P->sp<FaceEntry>(P->off_fent);
+        a.ftile = P->sp<int32_t>(P->off_ftile);
+        a.face_lds = P->face_lds;
+    }
     {
         const double A = P->h * P->h, eps = A * A * A;  // K A^3 with K = 1 (Sec. 4.2)
         a.eps2 = (float)(eps * eps);
@@ -789,6 +911,13 @@ sn_status sn_plan_init(sn_plan* P, const float* psi0, void* stream) {
     if (P->fluence)
         HIP_TRY(hipMemsetAsync(P->sp<char>(P->off_fluence), 0, (size_t)P->nx * P->ny * sizeof(double), s),
                 "clear fluence");
+    if (P->n_rects > 0) {
+        if (!P->fent_h.empty())
+            HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_fent), P->fent_h.data(), P->fent_h.size() * sizeof(FaceEntry),
+                                   hipMemcpyHostToDevice, s), "upload face entries");
+        HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_ftile), P->ftile_h.data(), P->ftile_h.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s), "upload face tiles");
+    }
     if (P->n_probes > 0) {
         if (!P->pent_h.empty())
             HIP_TRY(hipMemcpyAsync(P->sp<char>(P->off_pent), P->pent_h.data(), P->pent_h.size() * sizeof(ProbeEntry),
