@@ -89,7 +89,7 @@ constexpr uint32_t kDropOffset = 0x80000000u;
 template <>
 struct Store<float> {
     static __device__ __forceinline__ float2 load2(const char* p) { return *reinterpret_cast<const float2*>(p); }
-    static __device__ __forceinline__ float2 round2(float2 v, uint32_t, uint32_t) { return v; }
+    static __device__ __forceinline__ float2 round2(float2 v, uint32_t) { return v; }
     static __device__ __forceinline__ void store2(char* p, float2 v) { *reinterpret_cast<float2*>(p) = v; }
     static __device__ __forceinline__ void store1(char* p, float v) { *reinterpret_cast<float*>(p) = v; }
     static __device__ __forceinline__ float2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -133,18 +133,24 @@ struct Store<uint16_t> {
         const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
         return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
     }
-    // Stochastic rounding to bfloat16 with the random 16-bit values r0, r1
-    // (low halves): adding r to the magnitude bits below the kept 16 and
-    // truncating rounds up with probability equal to the discarded fraction,
-    // so the stored value is unbiased. Round-to-nearest would drop every
-    // update smaller than half a bfloat16 ulp (2^-9 relative) and let slowly
-    // changing fluxes stagnate. gfx950's v_cvt_sr_bf16_f32 does exactly this
-    // with the top 16 bits of its random operand (NaN quieted, Inf kept), one
-    // instruction per value, writing either half of the packed pair.
-    static __device__ __forceinline__ float2 round2(float2 v, uint32_t r0, uint32_t r1) {
+    // Stochastic rounding to bfloat16 with 16 random bits per value: adding
+    // them to the magnitude bits below the kept 16 and truncating rounds up
+    // with probability equal to the discarded fraction, so the stored value
+    // is unbiased. Round-to-nearest would drop every update smaller than half
+    // a bfloat16 ulp (2^-9 relative) and let slowly changing fluxes stagnate.
+    // gfx950's v_cvt_sr_bf16_f32 does exactly this with the top 16 bits of
+    // its random operand (NaN quieted, Inf kept), one instruction per value,
+    // writing either half of the packed pair. From one mixed word h: the
+    // first value takes low(h) ^ high(h), the second high(h), each in the top
+    // half of an operand whose low half is zero. h << 16 is formed with a
+    // byte permute: as a shift the compiler would fold it into a second
+    // (quarter-rate) integer multiply of the hash.
+    static __device__ __forceinline__ float2 round2(float2 v, uint32_t h) {
+        const uint32_t hi = h & 0xffff0000u;
+        const uint32_t lo = __builtin_amdgcn_perm(0u, h, 0x01000c0cu);  // h << 16
         bf16x2_t p = {0, 0};
-        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.x, r0 << 16, false);
-        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.y, r1 << 16, true);
+        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.x, lo ^ hi, false);
+        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.y, hi, true);
         const uint32_t u = __builtin_bit_cast(uint32_t, p);
         return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
     }
@@ -767,19 +773,17 @@ __device__ __forceinline__ void stage_ordinate(SArgs a, const OrdConst& o, int k
                 v.y = 0.5f * (oldv[t].y + v.y);
             }
             const uint32_t rowb = (uint32_t)(w.y0 + t + kGhost) * w.pitchb;
-            uint32_t r0 = 0, r1 = 0;
+            uint32_t h = 0;
             if (sizeof(T) == 2) {  // rounding bits from (stage, ordinate, cell pair of the plane)
                 const uint32_t sk = fmix32(fmix32(w.seed) + (uint32_t)k);  // wave-uniform
                 // per cell pair: a multiplicative (Fibonacci) hash of the key
-                // xor the pair's index, folded once. For a fixed cell the
-                // bits follow the key, uniform over stages and ordinates; one
-                // multiply instead of a second fmix32 (the stage is bound by
-                // its VALU issue with BF16 storage).
-                r0 = (sk ^ ((rowb + w.lane_off) / (uint32_t)sizeof(T))) * 0x9E3779B1u;
-                r0 ^= r0 >> 16;
-                r1 = r0 >> 16;  // the two halves of one mixed word, one per cell
+                // xor the pair's index, its two halves folded in round2. For a
+                // fixed cell the bits follow the key, uniform over stages and
+                // ordinates; one multiply instead of a second fmix32 (the
+                // stage is bound by its VALU issue with BF16 storage).
+                h = (sk ^ ((rowb + w.lane_off) / (uint32_t)sizeof(T))) * 0x9E3779B1u;
             }
-            v = Store<T>::round2(v, r0, r1);
+            v = Store<T>::round2(v, h);
             Store<T>::bstore2(rout, w.store_off, rowb, v);  // halo and partial lanes drop the pair
             if (w.ragged) Store<T>::bstore1(rout, w.single_off, rowb, v.x);
             if (w.ghost_wave) {
