@@ -234,3 +234,22 @@ def test_static_scratch_rejects_what_it_cannot_hold(L):
         assert "SN_STATIC_SCRATCH_BYTES" in lib.sn_last_error().decode()
     finally:
         lib.sn_plan_destroy(h)
+
+
+def test_crowded_rectangle_faces_accepted(L):
+    """Plan creation lists every rectangle-boundary face per tile with the
+    ring-slot offsets of the cells its trace needs, and rejects the plan if
+    one of those cells is not staged with the tile: rectangles crowding one
+    tile, straddling tile edges and lying on the grid's boundary, at every
+    order, storage type and launch shape."""
+    from paper_2505_17284_amd import solver
+
+    rects = [(0, 0, 260, 37), (0, 2, 200, 3), (3, 1, 125, 7), (127, 0, 129, 16)]
+    edge = [(259, 0, 260, 37), (0, 36, 260, 37), (128, 8, 129, 9), (0, 0, 1, 1)]
+    for rs in (rects, edge):
+        for order in (1, 2, 3):
+            for dtype in ("f32", "bf16"):
+                p = I.random_materials(260, 37, 4, seed=3, order=order, M=32, rects=rs, psi_dtype=dtype)
+                for rows, waves in ((2, 4), (4, 4), (2, 8), (4, 8)):
+                    info = solver.plan_info(p, rows_per_wave=rows, waves_per_group=waves)
+                    assert info["scratch_bytes"] > 0

@@ -2,9 +2,9 @@
 
 Every input comes from the seeded generators; every expected value from the
 oracle (or from a committed golden written by a script that calls only the
-oracle). Cases span several tiles (60 columns per wave, 4 waves per
-workgroup) with ragged tails in x and y, every boundary kind, both orders and
-both steppers, and the degenerate grids.
+oracle). Cases span several tiles (128 columns per wave, 4 waves of 2 rows
+per workgroup) with ragged tails in x and y, every boundary kind, both orders
+and both steppers, and the degenerate grids.
 """
 
 import json
@@ -82,11 +82,12 @@ def test_random_state_few_steps(sv, orc, order, stepper, bc):
     _check(p, g_, o_, 2)
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (61, 17), (64, 64), (121, 5)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (61, 17), (64, 64), (121, 5), (127, 8),
+                                   (128, 9), (129, 7), (257, 16)])
 @pytest.mark.parametrize("order", [1, 2])
 def test_degenerate_and_tile_edge_shapes(sv, orc, shape, order):
-    """Single cells, single rows/columns, and widths at tile boundaries
-    (60, 61, 120, 121 columns)."""
+    """Single cells, single rows/columns, and widths and heights at tile
+    boundaries (127, 128, 129, 257 columns; 7, 8, 9, 16 rows)."""
     nx, ny = shape
     rects = [(0, 0, nx, ny)]
     if nx >= 3 and ny >= 3:
@@ -109,6 +110,24 @@ def test_launch_shapes_agree(sv, orc, rows, waves, group):
     psi0 = I.random_state(p, 9, "smooth")
     g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0, group_size=group, rows_per_wave=rows,
                        waves_per_group=waves)
+    _check(p, g_, o_, 2)
+
+
+# Rectangles whose boundary faces crowd one tile (the first 128 x 8 tile
+# holds about 650 of them: the loader reads that tile's face table from LDS,
+# more than four entries per lane), one straddling a tile edge in x and a
+# tile row in y, edges on the grid's boundary.
+CROWDED_RECTS = [(0, 0, 260, 37), (0, 2, 200, 3), (3, 1, 125, 7), (127, 0, 129, 16)]
+
+
+@pytest.mark.parametrize("order,stepper", [(1, I.EULER), (2, I.HEUN), (3, I.HEUN)])
+def test_crowded_rectangle_faces(sv, orc, order, stepper):
+    """Outflow and inflow through many rectangle faces in one tile and across
+    tile edges: every QoI and field element against the oracle."""
+    p = I.random_materials(260, 37, 4, seed=31 + order, order=order, stepper=stepper, bc=BCS["mixed"][0],
+                           inflow=BCS["mixed"][1], M=32, h=0.05, t_end=1.0, rects=CROWDED_RECTS)
+    psi0 = I.random_state(p, 55, "smooth")
+    g_, o_ = _run_both(sv, orc, p, 2, psi0=psi0)
     _check(p, g_, o_, 2)
 
 

@@ -37,7 +37,7 @@ def test_random_state_few_steps(sv, orc, stepper, bc):
     _check(p, g_, o_, 2)
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (61, 17), (64, 64), (129, 5)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (61, 17), (64, 64), (128, 8), (129, 5), (257, 9)])
 def test_degenerate_and_tile_edge_shapes(sv, orc, shape):
     nx, ny = shape
     rects = [(0, 0, nx, ny)]
