@@ -125,8 +125,11 @@ constexpr uint32_t kFaceOffMask = 0x3fffu;
 constexpr int kFacePerLaneMax = 64;  // entries per loader lane (at most 64 x 64 faces per tile)
 // Entries a loader lane keeps in registers (orders 1 and 2; at order 3 the
 // limiter's operands would raise the kernel's register count); a tile with
-// more per lane reads them from a copy of its table in dynamic LDS.
-constexpr int kFaceRegs = 4;
+// more per lane reads them from a copy of its table in dynamic LDS. Three
+// cover a tile crossed by one rectangle edge along x plus a few along y (the
+// benchmark problems need at most three) and keep the batched kernel at
+// 4 workgroups per compute unit (91 VGPRs; four entries: 97, 3 workgroups).
+constexpr int kFaceRegs = 3;
 constexpr int face_regs(int order) { return order == 3 ? 0 : kFaceRegs; }
 
 // Ring slot layout (the stage kernels' LDS staging, also needed by the

@@ -983,11 +983,11 @@ __device__ __forceinline__ void stage_tile(SArgs a, int logical, FaceEntry* ftab
                 if (fl > face_regs(ORDER)) {
                     face_fluxes_lds<ORDER, T>(a, k, sb, ftab + lane * fl, fl, fout, fin);
                 } else {
+                    static_assert(kFaceRegs == 3, "one case per register count");
                     switch (fl) {
                     case 1: face_fluxes_regs<ORDER, T, 1>(a, k, sb, fr, fout, fin); break;
                     case 2: face_fluxes_regs<ORDER, T, 2>(a, k, sb, fr, fout, fin); break;
-                    case 3: face_fluxes_regs<ORDER, T, 3>(a, k, sb, fr, fout, fin); break;
-                    default: face_fluxes_regs<ORDER, T, 4>(a, k, sb, fr, fout, fin); break;
+                    default: face_fluxes_regs<ORDER, T, 3>(a, k, sb, fr, fout, fin); break;
                     }
                 }
             }
