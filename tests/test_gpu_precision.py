@@ -2,8 +2,10 @@
 
 The full lattice benchmark (700^2 cells, 256 ordinates, minmod, Heun, 640
 steps to T = 3.2) is solved with FP32 and with BF16 psi storage (FP32
-arithmetic in both) and every instantaneous and time-integrated QoI is
-compared with the oracle's values stored by tests/golden/make_oracle_goldens.py.
+arithmetic in both), and the full walled cavity (1300^2 cells, 64
+ordinates, 5200 steps) with BF16 storage; every instantaneous and
+time-integrated QoI is compared with the oracle's values stored by
+tests/golden/make_oracle_goldens.py.
 FP32 is held to the 1e-5 relative target. BF16 keeps 8 significant bits per
 stored value (stochastic rounding, so without bias); it is held to 1e-2
 relative or 1e-5 of the problem's scale (the largest QoI of the same kind),
@@ -37,15 +39,30 @@ def sv():
     return solver
 
 
+CAVITY_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_cavity1300_M64_heun2.json")
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_lattice700_full_run_error_per_qoi(sv, dtype):
-    if not os.path.exists(GOLDEN):
+    _full_run_error_per_qoi(sv, GOLDEN, I.config(2), dtype)
+
+
+def test_cavity1300_M64_bf16_full_run_error_per_qoi(sv):
+    """The walled cavity at full grid and length (1300^2, 5200 Heun steps),
+    one GPU's 64-ordinate share, BF16 storage, against the stored oracle run
+    (FP32 storage of the same run: tests/test_gpu_fullrun.py)."""
+    _full_run_error_per_qoi(sv, CAVITY_GOLDEN, I.cavity(1300, 64, name="cavity1300_M64_heun2"), "bf16")
+
+
+def _full_run_error_per_qoi(sv, golden, problem, dtype):
+    if not os.path.exists(golden):
         pytest.skip("golden not generated")
-    with open(GOLDEN) as f:
+    with open(golden) as f:
         gold = json.load(f)
-    p = I.config(2).replace(psi_dtype=dtype)
+    p = problem.replace(psi_dtype=dtype)
     print(f"[case] {p.name} psi {dtype}", flush=True)
     r = sv.solve(p)
+    assert r["nt"] == gold["nt"]
     print(f"| storage | QoI | oracle (FP64) | GPU | relative error |")
     for kind, g, o in (("at T", r["qoi"], gold["qoi"]), ("integrated", r["qoi_int"], gold["qoi_int"])):
         for name, ov in o.items():
