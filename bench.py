@@ -220,7 +220,7 @@ def time_tessellation(steps, dtype, N=22, warmup=2):
 def time_hohlraum(steps, dtype, n=1300, M=256, warmup=2):
     """The Hohlraum (layout Sec. 3.2.1, QoIs Sec. 3.2.2) at n^2 cells with every QoI on: the four
     probes' windows (QoI-1) and the fluence behind QoI-3 to QoI-6, timed
-    against the same solve without them."""
+    against the same solve without them (same launch shape)."""
     import torch
 
     from paper_2505_17284_amd import hohlraum
@@ -229,9 +229,14 @@ def time_hohlraum(steps, dtype, n=1300, M=256, warmup=2):
 
     p = I.hohlraum(n, M, psi_dtype=dtype)
     out = {"workload": f"hohlraum{n}_M{M}_heun2", "steps": steps}
-    for label, kw in (("plain", {}), ("with_qois", {"probes": hohlraum.probe_cells(p), "fluence": True})):
+    qois = {"probes": hohlraum.probe_cells(p), "fluence": True}
+    # both solves at the launch shape the one with QoIs takes by default
+    info = solver.plan_info(p, **qois)
+    shape = {k: info[k] for k in ("rows_per_wave", "waves_per_group", "group_size", "group_size_average")}
+    out["shape"] = shape
+    for label, kw in (("plain", {}), ("with_qois", qois)):
         print(f"[bench] hohlraum {label}: {p.name} {steps} steps", file=sys.stderr, flush=True)
-        plan = solver.Plan(p, device="cuda:0", **kw)
+        plan = solver.Plan(p, device="cuda:0", **shape, **kw)
         try:
             plan.run(warmup, unbounded=True)
             torch.cuda.synchronize()

@@ -186,12 +186,28 @@ sn_status validate_and_copy(const sn_problem* p, sn_plan* P) {
 
 void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* rows, int* waves) {
     // Two rows per wave keep the staged windows, the per-cell constants and the
-    // reconstructions within ~80 VGPRs. Four waves per workgroup: taller
-    // workgroups stage fewer halo rows but measured slower on the 700 x 700
-    // lattice. Ordinate groups as below; at least 8 ordinates per group keep
-    // the per-workgroup set-up and the group's phi partial small.
+    // reconstructions within ~80 VGPRs. Four waves per workgroup by default;
+    // ordinate groups as below; at least 8 ordinates per group keep the
+    // per-workgroup set-up and the group's phi partial small.
     *rows = 2;
     *waves = 4;
+    const int64_t cells = (int64_t)P->nx * P->ny;
+    // FP32 storage, orders 1 and 2, no probes: eight waves per workgroup
+    // (16-row tiles stage 1.25x instead of 1.5x the stencil rows) on grids of
+    // 10^6 cells or more, and of 4 10^5 or more with 512 ordinates or more,
+    // 32 ordinates per group in both stages. Timed over minmod-Heun lattice
+    // and cavity classes (grid side 200 to 1300, 64 to 512 ordinates, ms per
+    // step against four waves): the 1300^2 x 512 cavity 3.58 -> 3.48, the
+    // 1000^2 lattice 2.6-6% faster at every ordinate count, 700^2 x 512 4%;
+    // slower on smaller grids (700^2 x 256: +2%), at order 3 (1.22 vs 0.95 ms
+    // on the 700^2 lattice) and with BF16 storage (+5-15%).
+    if (P->dtype == SN_F32 && P->order < 3 && P->n_probes == 0 &&
+        (cells >= 1000000 || (cells >= 400000 && P->M >= 512))) {
+        *waves = 8;
+        *group_size = std::min(P->M, 32);
+        *group_size_avg = *group_size;
+        return;
+    }
     const int wg_rows = *waves * *rows;
     const long tiles = (long)((P->nx + kTileX - 1) / kTileX) * ((P->ny + wg_rows - 1) / wg_rows);
     if (P->dtype == SN_F32) {
@@ -203,9 +219,18 @@ void default_shape(const sn_plan* P, int* group_size, int* group_size_avg, int* 
         // at 4 K workgroups had split mid-size grids into groups of 8 (500^2 x
         // 256: 0.42 vs 0.31 ms per step). More than 32 per group is slower on
         // large M (700 x 700 with 1936 ordinates, stage 1: 1.83 ms with 32
-        // per group, 2.27 ms with 242).
+        // per group, 2.27 ms with 242). Launches of 1,000 to 5,000 workgroups
+        // at 32 per group take 16 (re-timed after the face currents left the
+        // compute waves, which freed LDS for a fourth workgroup per compute
+        // unit: the 700^2 lattice 1.9-6% faster at 64 to 256 ordinates,
+        // 560^2 and 400^2 1.3-2%; the 700^2 x 256 benchmark lattice 0.525 ->
+        // 0.515 ms per step).
         int gs = std::min(P->M, 32);
         while (gs > 8 && tiles * ((P->M + gs - 1) / gs) < 400) gs = (gs + 1) / 2;
+        if (gs == 32 && P->order < 3) {  // order 3 (bound by its arithmetic) not re-timed
+            const long wg = tiles * ((P->M + gs - 1) / gs);
+            if (wg >= 1000 && wg < 5000) gs = 16;
+        }
         *group_size = gs;
     } else {
         // BF16 storage favours larger groups: 64 ordinates per group (M / 8

@@ -194,27 +194,33 @@ def test_probe_statements(L):
 
 
 def test_default_launch_shapes(L):
-    """The default ordinate groups of the measured workloads (host only):
-    32 per group on the benchmark lattice with the averaging stage halved, 32
-    on the cavity (not halved: more than 2^20 cells) and on one GPU's
-    64-ordinate share of it, fewer on grids too small to fill the GPU
-    otherwise, and no halving with BF16 storage, the Venkatakrishnan limiter
-    or fewer than 256 ordinates; BF16 storage takes groups of 64."""
+    """The default launch shapes of the measured workloads (host only): with
+    FP32 storage eight waves per workgroup and 32 ordinates per group on grids
+    of 10^6 cells or more (the cavity and one GPU's 64-ordinate share of it)
+    and on 4 10^5 or more with 512 ordinates; otherwise four waves, 16
+    ordinates per group where 32 would give 1,000 to 5,000 workgroups (the
+    benchmark lattice, 560^2 at 128 and 256 ordinates), 32 with the averaging
+    stage halved above that at 256 ordinates or more (560^2 x 512), fewer on
+    grids too small to fill the GPU otherwise; no such change with the
+    Venkatakrishnan limiter; BF16 storage keeps four waves and groups of 64."""
     from paper_2505_17284_amd import solver
 
     def g(p):
         i = solver.plan_info(p)
         return i["group_size"], i["group_size_average"], i["rows_per_wave"], i["waves_per_group"]
 
-    assert g(I.config(2)) == (32, 16, 2, 4)
+    assert g(I.config(2)) == (16, 16, 2, 4)
     assert g(I.config(2).replace(psi_dtype="bf16")) == (64, 64, 2, 4)
     assert g(I.config(2).replace(order=3)) == (32, 32, 2, 4)
-    assert g(I.config(3)) == (32, 32, 2, 4)
-    assert g(I.cavity(1300, 64)) == (32, 32, 2, 4)
+    assert g(I.config(3)) == (32, 32, 2, 8)
+    assert g(I.config(3).replace(psi_dtype="bf16")) == (64, 64, 2, 4)
+    assert g(I.cavity(1300, 64)) == (32, 32, 2, 8)
     assert g(I.lattice(140, 64, order=2, stepper=I.HEUN)) == (8, 8, 2, 4)
     assert g(I.lattice(140, 256, order=2, stepper=I.HEUN)) == (16, 16, 2, 4)
-    assert g(I.lattice(560, 128, order=2, stepper=I.HEUN)) == (32, 32, 2, 4)
-    assert g(I.lattice(560, 256, order=2, stepper=I.HEUN)) == (32, 16, 2, 4)
+    assert g(I.lattice(560, 128, order=2, stepper=I.HEUN)) == (16, 16, 2, 4)
+    assert g(I.lattice(560, 256, order=2, stepper=I.HEUN)) == (16, 16, 2, 4)
+    assert g(I.lattice(560, 512, order=2, stepper=I.HEUN)) == (32, 16, 2, 4)
+    assert g(I.lattice(700, 512, order=2, stepper=I.HEUN)) == (32, 32, 2, 8)
 
 
 def test_static_scratch_rejects_what_it_cannot_hold(L):
