@@ -47,13 +47,15 @@ def qoi_scale(inst: dict, integ: dict) -> tuple:
 
 
 def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rtol: float = QOI_RTOL,
-                per_qoi: bool = False, rtol_for: dict | None = None):
+                per_qoi: bool = False, rtol_for: dict | None = None, rtol_for_int: dict | None = None):
     """Returns (ok, report) comparing every named QoI; rtol_for maps QoI names
-    to their own relative tolerance (each derived where it is used)."""
+    to their own relative tolerance (each derived where it is used), for the
+    time integrals too unless rtol_for_int gives theirs."""
     s_inst, s_int = qoi_scale(orc_inst, orc_int)
     ok = True
     lines = []
     for kind, g, o, scale in (("inst", gpu_inst, orc_inst, s_inst), ("int", gpu_int, orc_int, s_int)):
+        own = (rtol_for_int if kind == "int" and rtol_for_int is not None else rtol_for) or {}
         for name in o:
             if name not in g:
                 continue
@@ -66,7 +68,7 @@ def compare_qoi(gpu_inst: dict, gpu_int: dict, orc_inst: dict, orc_int: dict, rt
                 ref = abs(float(o.get("out:" + r, 0.0))) + abs(float(o.get("in:" + r, 0.0)))
             if ref >= floor:
                 rel = err / ref
-                good = rel <= (rtol_for or {}).get(name, rtol)
+                good = rel <= own.get(name, rtol)
                 tag = "" if ref == abs(ov) else " (of gross current)"
                 lines.append(f"{kind:4s} {name:14s} orc={ov:.12g} gpu={gv:.12g} rel={rel:.2e}{tag}{'' if good else '  FAIL'}")
             else:

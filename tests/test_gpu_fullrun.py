@@ -7,7 +7,8 @@
 * The walled cavity at its full grid and length (1300^2 cells, 5200 Heun
   steps to T = 2.6, sigma_t = 100 walls and block) with the 4 x 16 product
   quadrature (64 ordinates, one GPU's share of an 8-way ordinate split of the
-  512): every QoI at 1e-5 relative.
+  512): every QoI at 1e-5 relative but the outflow from the block at T,
+  held to 1e-4 (below).
 
 The oracle values are written by tests/golden/make_oracle_goldens.py, which
 calls only the FP64 oracle. QoIs are held to 1e-5 of their own value (the
@@ -20,6 +21,16 @@ draw: an independent float32 NumPy model of the scheme (tests/fp32_model.py,
 coefficients rounded once, FP32 state and arithmetic) lands 4.2e-6 (seed 2)
 and 2.8e-5 (seed 9) from the FP64 oracle on it, while every other QoI of
 those draws stays within 3.1e-6.
+
+The cavity's outflow from the block is the same kind of quantity: the
+radiation that leaves a sigma_a = 100 block, 4e-3 of what enters it, made of
+the smallest psi values beside the block's surface. FP32 storage alone moves
+its value at T by 0.8e-6 to 6.2e-5 of itself over the cavity at 130^2 to
+1300^2 cells (64 ordinates, to T): the float32 model lands 6.2e-5, 2.1e-5,
+8.0e-7 and 1.9e-6 from the oracle at n = 130, 260, 520, 1300 and this path
+3.1e-5, 2.1e-5, 7.9e-7 and 1.1e-5, while every other QoI of those runs stays
+within 1.4e-6 on both. It is held to 1e-4 at T (1.6x the largest model
+drift); its time integral stays at 1e-5.
 """
 
 import json
@@ -33,7 +44,7 @@ from tests.parity import compare_qoi
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-DEEP_OUTFLOW_RTOL = 1e-4  # the draws' outer-boundary outflow (module docstring)
+DEEP_OUTFLOW_RTOL = 1e-4  # the draws' outer-boundary outflow, the cavity's outflow from the block at T (module docstring)
 
 
 @pytest.fixture(scope="module")
@@ -86,6 +97,7 @@ def test_cavity1300_M64_full_length(gpu):
     print(f"[case] {p.name} to T ({gold['nt']} steps)", flush=True)
     r = solver.solve(p)
     assert r["nt"] == gold["nt"] == 5200
-    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], per_qoi=True)
+    ok, rep = compare_qoi(r["qoi"], r["qoi_int"], gold["qoi"], gold["qoi_int"], per_qoi=True,
+                          rtol_for={"out:block": DEEP_OUTFLOW_RTOL}, rtol_for_int={})
     print(rep, flush=True)
     assert ok, rep
