@@ -220,12 +220,28 @@ __device__ __forceinline__ float venkat_pair(float A, float b_up, float b_dn, fl
 // and ay = (N - S)/4 (the Green-Gauss gradient of a square cell is the
 // central difference). Face values: c + L ax (east), c - L ax (west), c + L
 // ay (north), c - L ay (south).
+// The largest and smallest of three values, one instruction each. (Through
+// fmaxf / fminf the compiler first quiets every operand that may be a
+// signalling NaN, one more instruction per operand, because it cannot tell
+// that staged values never are; for the values this code compares the
+// results are the same.)
+__device__ __forceinline__ float max3f(float a, float b, float c) {
+    float r;
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ float min3f(float a, float b, float c) {
+    float r;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ float venkat_limit(float c, float W, float E, float S, float N, float e2, float& ax,
                                               float& ay) {
     ax = 0.25f * (E - W);
     ay = 0.25f * (N - S);
-    const float mx = fmaxf(fmaxf(fmaxf(W, E), fmaxf(S, N)), c);
-    const float mn = fminf(fminf(fminf(W, E), fminf(S, N)), c);
+    const float mx = max3f(max3f(W, E, S), N, c);
+    const float mn = min3f(min3f(W, E, S), N, c);
     const float b_up = mx - c, b_dn = c - mn;
     return fminf(venkat_pair(fabsf(ax), b_up, b_dn, e2), venkat_pair(fabsf(ay), b_up, b_dn, e2));
 }
