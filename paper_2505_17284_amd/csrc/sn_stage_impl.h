@@ -140,17 +140,18 @@ struct Store<uint16_t> {
     // a bfloat16 ulp (2^-9 relative) and let slowly changing fluxes stagnate.
     // gfx950's v_cvt_sr_bf16_f32 does exactly this with the top 16 bits of
     // its random operand (NaN quieted, Inf kept), one instruction per value,
-    // writing either half of the packed pair. From one mixed word h: the
-    // first value takes low(h) ^ high(h), the second high(h), each in the top
-    // half of an operand whose low half is zero. h << 16 is formed with a
-    // byte permute: as a shift the compiler would fold it into a second
-    // (quarter-rate) integer multiply of the hash.
+    // writing either half of the packed pair; the low half of the random
+    // operand is not read (whole solves are bit-identical with it cleared).
+    // From one mixed word h: the first value takes low(h) ^ high(h), the
+    // second high(h). h << 16 is formed with a byte permute: as a shift the
+    // compiler would fold it into a second (quarter-rate) integer multiply of
+    // the hash. The pair starts from h's bits, both halves overwritten, so no
+    // register is cleared first.
     static __device__ __forceinline__ float2 round2(float2 v, uint32_t h) {
-        const uint32_t hi = h & 0xffff0000u;
-        const uint32_t lo = __builtin_amdgcn_perm(0u, h, 0x01000c0cu);  // h << 16
-        bf16x2_t p = {0, 0};
-        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.x, lo ^ hi, false);
-        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.y, hi, true);
+        const uint32_t r0 = __builtin_amdgcn_perm(0u, h, 0x01000c0cu) ^ h;  // top half: low(h) ^ high(h)
+        bf16x2_t p = __builtin_bit_cast(bf16x2_t, h);
+        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.y, h, true);
+        p = __builtin_amdgcn_cvt_sr_bf16_f32(p, v.x, r0, false);
         const uint32_t u = __builtin_bit_cast(uint32_t, p);
         return make_float2(bf16_widen(u & 0xffffu), bf16_widen(u >> 16));
     }
