@@ -113,6 +113,22 @@ def test_launch_shapes_agree(sv, orc, rows, waves, group):
     _check(p, g_, o_, 2)
 
 
+@pytest.mark.parametrize("rows", [2, 4])
+@pytest.mark.parametrize("waves", [4, 8])
+@pytest.mark.parametrize("order", [1, 2])
+def test_launch_shapes_across_tiles(sv, orc, rows, waves, order):
+    """Every launch shape on a grid three tiles wide whose last tile holds
+    3 columns, rough initial state: the x-halo cells a tile reads from its
+    neighbours' edge records (and from psi's ghost cells on the grid's
+    sides) are the oracle's neighbours, for every record height."""
+    p = I.random_materials(259, 21, 4, seed=order * 7 + rows + waves, order=order, stepper=I.HEUN,
+                           bc=BCS["mixed"][0], inflow=BCS["mixed"][1], M=32, h=0.05,
+                           rects=[(0, 0, 259, 21), (120, 3, 131, 18), (250, 1, 258, 20)])
+    psi0 = I.random_state(p, 21, "uniform")
+    g_, o_ = _run_both(sv, orc, p, 3, psi0=psi0, rows_per_wave=rows, waves_per_group=waves)
+    _check(p, g_, o_, 3)
+
+
 # Rectangles whose boundary faces crowd one tile (the first 128 x 8 tile
 # holds about 650 of them: the loader reads that tile's face table from LDS,
 # more than four entries per lane), one straddling a tile edge in x and a
