@@ -483,7 +483,7 @@ def main():
 
     if args.uq:
         print(f"[bench] batched UQ: {args.uq} lattice draws", file=sys.stderr, flush=True)
-        line["batched_uq"] = serve.uq(args.uq, verbose=True, tune=True, compare_default=True)
+        line["batched_uq"] = serve.uq(args.uq, verbose=True, compare_tuned=True)
     if args.serving_requests:
         loads = tuple(float(x) for x in args.serving_loads.split(","))
         print(f"[bench] serving: {args.serving_requests} requests at loads {loads}", file=sys.stderr, flush=True)

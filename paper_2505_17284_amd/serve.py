@@ -296,13 +296,15 @@ def same_results(rec_a, rec_b, rtol: float = 1e-5):
 
 def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_alone: bool = True,
        psi_dtype: str = "f32", verbose: bool = False, tune: bool = False, compare_default: bool = False,
-       direct_per_cu: int = 4):
+       direct_per_cu: int = 4, compare_tuned: bool = False):
     """The batched UQ workload: DP-2 lattice draws, all admitted at once, run to T.
     tune: admit every draw with the ordinate groups `solver.autotune` measures
     for its (grid, ordinates) class (tuning time reported apart, not in
     wall_s); the one-at-a-time comparison then uses the same groups, so that
     speedup_vs_alone is the batching's alone. compare_default: also run the
     batch with the library's default groups (speedup_vs_default_shapes).
+    compare_tuned (with tune False): also run the batch with the autotuned
+    groups (tuned_wall_s, tuned_tune_s, speedup_tuned_vs_default).
     direct_per_cu: plans with at least this many workgroups per compute unit
     take launches of their own (the library's default is 2; with many small
     plans at once, as here, 4 measured faster: 15.3 vs 16.4 s)."""
@@ -348,6 +350,12 @@ def uq(n_instances: int = 256, seed0: int = 0, steps_per_run: int = 16, compare_
                direct_per_cu=direct_per_cu)
         out["default_shapes_wall_s"] = d["wall_s"]
         out["speedup_vs_default_shapes"] = d["wall_s"] / secs
+    if compare_tuned and not tune:
+        t = uq(n_instances, seed0, steps_per_run, compare_alone=False, psi_dtype=psi_dtype, tune=True,
+               direct_per_cu=direct_per_cu)
+        out["tuned_wall_s"] = t["wall_s"]
+        out["tuned_tune_s"] = t["tune_s"]
+        out["speedup_tuned_vs_default"] = secs / t["wall_s"]
     if compare_alone:
         _sync()
         t0 = time.perf_counter()
