@@ -88,7 +88,7 @@ struct StageArgs {
     int32_t nx, ny, pitch, M;
     int32_t ox;             // column of interior cell 0 in a row
     int32_t G, Mg;          // ordinate groups and ordinates per group
-    int32_t ntx, nty;       // tiles along x (124 columns) and y (waves * rows_per_wave rows)
+    int32_t ntx, nty;       // tiles along x (128 columns) and y (waves * rows_per_wave rows)
     int32_t n_wg;
     int32_t n_tallies, n_rects, nq;
     int32_t bc[4];

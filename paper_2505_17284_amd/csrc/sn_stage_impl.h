@@ -9,8 +9,10 @@
 //          - dt sigma_t psi + dt sigma_s / (2 pi) phi + dt Q,
 //
 // with the upwind trace of eq. eq_upwind1stOrder: the upwind cell's value for
-// first order, or its minmod-limited linear reconstruction at the face for
-// second order. The stage update follows Sec. 4.3 (eq. eq_ODE): psi + dt F
+// first order, its minmod-limited linear reconstruction at the face for
+// second order, or (the third template order) its Green-Gauss gradient
+// reconstruction with the Venkatakrishnan limiter of Sec. 4.2 (eq.
+// eq_V_limiter). The stage update follows Sec. 4.3 (eq. eq_ODE): psi + dt F
 // (Euler and Heun's first stage) or (psi^n + psi^(1) + dt F(psi^(1))) / 2
 // (Heun's second stage, written in place over psi^n). The scalar flux
 // phi = sum_k w_k psi_k of the written state (Sec. 4.1) leaves as a per-group
@@ -37,9 +39,10 @@
 // while they compute earlier ordinates. The loader wave also sums the QoIs
 // that need few cells: the currents through rectangle boundaries and the
 // space-time probes. Per-cell material data and the incoming scalar flux
-// stay in registers across the ordinate loop. Global accesses are buffer instructions: one scalar resource per
-// plane, wave-uniform row offsets, one per-lane offset.
-// There is no MFMA: the stage is a bandwidth-bound stencil.
+// stay in registers across the ordinate loop. Global accesses are buffer
+// instructions: one scalar resource per plane, wave-uniform row offsets, one
+// per-lane offset. There is no MFMA: the stage is a bandwidth-bound stencil
+// (order 3: bound by its arithmetic, still no contraction).
 #pragma once
 
 #include <hip/hip_runtime.h>
