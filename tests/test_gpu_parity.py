@@ -320,12 +320,14 @@ def test_lattice700_full_run_matches_golden(sv):
     assert ok, rep
 
 
-@pytest.mark.parametrize("N,order", [(5, 2), (22, 2), (22, 1)])
+@pytest.mark.parametrize("N,order", [(5, 2), (22, 2), (22, 1), (5, 3), (22, 3)])
 def test_tessellation_quadrature_random_state(sv, orc, N, order):
     """The paper's tessellation quadrature (M = 4 N^2: 100, and 1936 at the
     finest N = 22, where ordinate groups run to ~242 ordinates): every element
     of psi and phi and every QoI after two Heun steps from a random state on a
-    ragged lattice grid with reflective and inflow sides."""
+    ragged lattice grid with reflective and inflow sides, for every order
+    (at order 3 the reflective ghosts of every ordinate come from its
+    mirror in this quadrature)."""
     p = I.lattice(71, order=order, stepper=I.HEUN, quad=I.tessellation_quadrature(N),
                   bc=(I.BC_REFLECT, I.BC_INFLOW, I.BC_REFLECT, I.BC_VACUUM))
     p = p.replace(inflow=(0.0, 0.6, 0.0, 0.0))
